@@ -1,0 +1,404 @@
+"""CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+A plain, exact reference for the self-adaptive Ising machine (SAIM) of
+Delacour, "Self-Adaptive Ising Machines for Constrained Optimization".  Only
+tests/, the smoke check and the bench's CPU-baseline leg may import this
+module; the product path never does.  It shares no code with the HIP path:
+the only thing both import is the seeded instance generator module.
+
+Python ints and fractions.Fraction carry every scalar exactly; the per-visit
+sampling loop lives in sa_oracle.c (same directory) and is called through
+ctypes.
+
+What it follows, step by step:
+
+* Problem and encoding (Sec. II Eq. primal_problem; Sec. IV-A, IV-B):
+  maximise profit(x) s.t. A x <= b.  Each inequality becomes an equality with
+  Q_k = floor(log2 b_k + 1) binary slack bits of weights 2^q; W and h are
+  zero-padded for the slack bits.  QKP: h = diagonal of the profit matrix,
+  W = its off-diagonal part, so profit = h.x + sum_{i<j} W_ij x_i x_j.
+* Normalisation (Sec. IV-A): profits are divided by s_f = max(|W|,|h|), the
+  constraint data by s_g = max(|A|,|b|).
+* Lagrangian (Eq. penalty_energy, Eq. Lagrange_energy), normalised:
+  L_n = -profit/s_f + P_n |g|^2/s_g^2 + lambda_n . g/s_g,  g = A_ext x - b,
+  with P_n = Pq/256 and lambda_n = lq/256.  D = 256 s_f s_g^2 makes D L_n an
+  integer.
+* Penalty rule (Sec. III-A): P = alpha d N with N counting slack spins;
+  d = nominal pair density (QKP) or 2/(N+1) (MKP, Sec. IV-B).
+* p-bit machine (Sec. III-B, Eq. Ii_eq, Eq. mi_eq, Eq. Boltzmann_distrib):
+  sequential Gibbs sweeps, beta linear from 0 to beta_max over the run, the
+  last state is the sample.  P(x_i = 1) = (1 + tanh(beta I_i))/2 with
+  I_i = -(dL_n)/2, quantised to a 2^-8 grid in beta*I and a 24-bit threshold.
+* Algorithm 1: lambda starts at 0; after each run lambda += eta g(x) (here
+  the mean over replicas, normalised by s_g); feasible samples are kept and the
+  best one returned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from decimal import ROUND_HALF_EVEN, Decimal, localcontext
+from fractions import Fraction
+from functools import lru_cache
+from math import floor
+
+import numpy as np
+
+from paper_2501_04971_amd.generators import KIND_MKP, KIND_QKP, Params, Problem
+
+THETA_HALF = 2304          # table covers beta*I in [-9, 9] at 2^-8 resolution
+ONE24 = 1 << 24
+ZBUDGET = 1 << 61          # every local field stays below 2^62 in magnitude
+LQ_CAP = 1 << 24           # lambda_n never exceeds 2^16 in magnitude
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_BUILD = os.path.join(_HERE, "_build")
+_SO = os.path.join(_BUILD, "libsa_oracle.so")
+
+
+class OracleRangeError(ValueError):
+    """Instance whose exact integer fields would not fit the stated bounds."""
+
+
+# ---------------------------------------------------------------------------
+# exact helpers
+
+def round_half_away(v: Fraction) -> int:
+    if v >= 0:
+        return floor(v + Fraction(1, 2))
+    return -floor(-v + Fraction(1, 2))
+
+
+def round_half_up(v: Fraction) -> int:
+    return floor(v + Fraction(1, 2))
+
+
+@lru_cache(maxsize=1)
+def theta_table() -> tuple:
+    """Theta[j] = round(2^24 (1 + tanh(j/256))/2) = round(2^24 / (1 + e^(-2j/256))),
+    j = -2304..2304, evaluated with 60 significant decimal digits."""
+    out = []
+    with localcontext() as ctx:
+        ctx.prec = 60
+        for j in range(-THETA_HALF, THETA_HALF + 1):
+            v = Decimal(ONE24) / (Decimal(1) + (Decimal(-2 * j) / Decimal(256)).exp())
+            out.append(int(v.to_integral_value(rounding=ROUND_HALF_EVEN)))
+    return tuple(out)
+
+
+# ---------------------------------------------------------------------------
+# the encoded instance
+
+@dataclass
+class Program:
+    kind: int
+    n: int                 # original variables
+    m: int                 # constraints
+    n_ext: int             # spins including slack bits
+    Q: list                # slack bits per constraint
+    slack: list            # (k, q) for sites n .. n_ext-1
+    W: np.ndarray          # (n_ext, n_ext) int64 pair profits, zero diagonal
+    h: np.ndarray          # (n_ext,) int64 item profits
+    A: np.ndarray          # (m, n_ext) int64 extended constraint matrix
+    b: np.ndarray          # (m,) int64
+    s_f: int
+    s_g: int
+    D: int
+    pq: int                # 256 * P_n
+    T: int
+    S: int
+    B: list                # beta grid, one value per sweep
+    lq_max: int
+    eta: Fraction
+    R: int
+    seed: int
+    inst: int
+
+    def beta_values(self) -> list:
+        """beta_t implied by the grid (for documentation and tests)."""
+        return [Fraction(2 * self.s_f * self.s_g * self.s_g * bt, 1 << self.S) for bt in self.B]
+
+
+def build_program(prob: Problem, par: Params) -> Program:
+    n, m = prob.n, prob.m
+    A0 = np.asarray(prob.weight, dtype=np.int64).reshape(m, n)
+    b0 = np.asarray(prob.capacity, dtype=np.int64).reshape(m)
+    if (A0 < 0).any() or (b0 < 0).any():
+        raise ValueError("weights and capacities must be non-negative")
+    if prob.kind == KIND_QKP:
+        P = np.asarray(prob.profit, dtype=np.int64).reshape(n, n)
+        if not (P == P.T).all():
+            raise ValueError("QKP profit matrix must be symmetric")
+        h0 = np.diag(P).copy()
+        W0 = P.copy()
+        np.fill_diagonal(W0, 0)
+    elif prob.kind == KIND_MKP:
+        h0 = np.asarray(prob.profit, dtype=np.int64).reshape(n)
+        W0 = np.zeros((n, n), dtype=np.int64)
+    else:
+        raise ValueError("unknown problem kind")
+
+    # slack bits: Q_k = floor(log2 b_k + 1) = bit length of b_k
+    Q = [int(bk).bit_length() for bk in b0]
+    slack = [(k, q) for k in range(m) for q in range(Q[k])]
+    n_ext = n + len(slack)
+    A = np.zeros((m, n_ext), dtype=np.int64)
+    A[:, :n] = A0
+    for s, (k, q) in enumerate(slack):
+        A[k, n + s] = 1 << q
+    W = np.zeros((n_ext, n_ext), dtype=np.int64)
+    W[:n, :n] = W0
+    h = np.zeros(n_ext, dtype=np.int64)
+    h[:n] = h0
+
+    # normalisation maxima over the original data
+    s_f = max(1, int(np.abs(h0).max(initial=0)), int(np.abs(W0).max(initial=0)))
+    s_g = max(1, int(A0.max(initial=0)), int(b0.max(initial=0)))
+    D = 256 * s_f * s_g * s_g
+
+    # penalty
+    if par.p_q is not None:
+        pq = int(par.p_q)
+        if pq < 0:
+            raise ValueError("p_q must be >= 0")
+    else:
+        d = Fraction(prob.density) if prob.kind == KIND_QKP else Fraction(2, n_ext + 1)
+        pq = round_half_away(256 * Fraction(par.alpha) * d * n_ext)
+
+    # beta grid: B_t = round(2^S beta_t / (2 s_f s_g^2)); S smallest with B_last >= 2^30
+    T = int(par.sweeps)
+    if T < 1:
+        raise ValueError("sweeps must be >= 1")
+    beta = Fraction(par.beta)
+    if beta < 0:
+        raise ValueError("beta must be >= 0")
+
+    def beta_t(t: int) -> Fraction:
+        if par.fixed_beta or T == 1:
+            return beta
+        return beta * t / (T - 1)
+
+    den = 2 * s_f * s_g * s_g
+    if beta == 0:
+        S = 32
+    else:
+        S = 1
+        while round_half_up(Fraction(1 << S) * beta / den) < (1 << 30):
+            S += 1
+            if S > 94:
+                raise OracleRangeError("beta grid shift out of range")
+    B = [round_half_up(Fraction(1 << S) * beta_t(t) / den) for t in range(T)]
+
+    # bounds that keep every field inside int64 (|Z| < 2^62)
+    absA = A  # non-negative
+    E = absA.sum(axis=0)                                  # sum_k |a_ki|
+    amax = int(E.max(initial=0))
+    sq = (absA * absA).sum(axis=0)
+    gmax = 0
+    for k in range(m):
+        tot = int(absA[k].sum())
+        gmax = max(gmax, int(b0[k]), tot - int(b0[k]))
+    fmax = int((np.abs(h) + np.abs(W).sum(axis=1)).max(initial=0))
+    zmax0 = 256 * s_g * s_g * fmax + s_f * pq * (2 * amax * gmax + int(sq.max(initial=0)))
+    if zmax0 >= ZBUDGET:
+        raise OracleRangeError("instance fields exceed the 2^61 budget")
+    if amax == 0:
+        lq_max = LQ_CAP
+    else:
+        lq_max = min(LQ_CAP, (ZBUDGET - zmax0) // (s_f * s_g * amax))
+    if lq_max < 256:
+        raise OracleRangeError("multiplier range below 1.0")
+
+    return Program(prob.kind, n, m, n_ext, Q, slack, W, h, A, b0.copy(), s_f, s_g, D, pq, T, S,
+                   B, lq_max, Fraction(par.eta), int(par.replicas), int(par.seed),
+                   int(par.instance_id))
+
+
+# ---------------------------------------------------------------------------
+# energy and scoring from the definitions
+
+def residual(prog: Program, x: np.ndarray) -> np.ndarray:
+    """g = A_ext x - b for one or many extended states (last axis = sites)."""
+    x = np.asarray(x, dtype=np.int64)
+    return x @ prog.A.T - prog.b
+
+
+def profit_ext(prog: Program, x: np.ndarray):
+    """h.x + sum_{i<j} W_ij x_i x_j (slack sites carry no profit)."""
+    x = np.asarray(x, dtype=np.int64)
+    quad = ((x @ prog.W) * x).sum(axis=-1) // 2
+    return x @ prog.h + quad
+
+
+def energy(prog: Program, x, lq) -> int:
+    """D * L_n(x) for one extended state, as an exact Python int."""
+    x = [int(v) for v in x]
+    g = [int(v) for v in residual(prog, np.array(x, dtype=np.int64))]
+    prof = int(profit_ext(prog, np.array(x, dtype=np.int64)))
+    return (-256 * prog.s_g * prog.s_g * prof + prog.s_f * prog.pq * sum(v * v for v in g)
+            + prog.s_f * prog.s_g * sum(int(l) * v for l, v in zip(lq, g)))
+
+
+def score(prog: Program, x: np.ndarray):
+    """Per replica: (profit of the original bits, feasible of A x <= b) (Sec. IV-A)."""
+    x = np.asarray(x, dtype=np.int64)
+    xo = x[..., :prog.n]
+    A0 = prog.A[:, :prog.n]
+    feasible = ((xo @ A0.T) <= prog.b).all(axis=-1)
+    W0 = prog.W[:prog.n, :prog.n]
+    profit = xo @ prog.h[:prog.n] + ((xo @ W0) * xo).sum(axis=-1) // 2
+    return profit, feasible
+
+
+def index_of(prog: Program, Z: int, t: int) -> int:
+    """clamp(floor((Z B_t + 2^(S-1)) / 2^S), -2304, 2304)."""
+    q = (int(Z) * prog.B[t] + (1 << (prog.S - 1))) >> prog.S
+    return max(-THETA_HALF, min(THETA_HALF, q))
+
+
+# ---------------------------------------------------------------------------
+# multiplier update (Algorithm 1, with the replica mean of g)
+
+def lambda_step(prog: Program, lam_acc: list, G: list, R: int | None = None):
+    """lam_acc on a 2^-32 grid of lambda_n; returns (new lam_acc, lq on 2^-8 grid)."""
+    R = prog.R if R is None else R
+    cap = prog.lq_max << 24
+    new_acc, lq = [], []
+    for acc, Gk in zip(lam_acc, G):
+        delta = round_half_away(Fraction(1 << 32) * prog.eta * int(Gk) / (R * prog.s_g))
+        acc = max(-cap, min(cap, int(acc) + delta))
+        new_acc.append(acc)
+        lq.append(round_half_away(Fraction(acc, 1 << 24)))
+    return new_acc, lq
+
+
+# ---------------------------------------------------------------------------
+# the C sampling core
+
+class _Prog(ctypes.Structure):
+    _fields_ = [
+        ("n_ext", ctypes.c_int32), ("m", ctypes.c_int32), ("T", ctypes.c_int32),
+        ("S", ctypes.c_int32),
+        ("W", ctypes.c_void_p), ("h", ctypes.c_void_p), ("A", ctypes.c_void_p),
+        ("b", ctypes.c_void_p),
+        ("s_f", ctypes.c_int64), ("s_g", ctypes.c_int64), ("pq", ctypes.c_int64),
+        ("B", ctypes.c_void_p), ("theta", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64), ("inst", ctypes.c_uint32),
+    ]
+
+
+def build_library(force: bool = False) -> str:
+    """Compiles sa_oracle.c with gcc (plain C, -O2) into oracle/_build."""
+    src = os.path.join(_HERE, "sa_oracle.c")
+    if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= os.path.getmtime(src):
+        return _SO
+    os.makedirs(_BUILD, exist_ok=True)
+    tmp = _SO + f".tmp{os.getpid()}"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", src, "-o", tmp],
+                   check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+@lru_cache(maxsize=1)
+def _lib():
+    lib = ctypes.CDLL(build_library())
+    lib.oracle_sa_round.argtypes = [ctypes.POINTER(_Prog), ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int32]
+    lib.oracle_sa_round.restype = ctypes.c_int
+    lib.oracle_local_field.argtypes = [ctypes.POINTER(_Prog), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int32]
+    lib.oracle_local_field.restype = ctypes.c_int64
+    lib.oracle_index.argtypes = [ctypes.POINTER(_Prog), ctypes.c_int64, ctypes.c_int32]
+    lib.oracle_index.restype = ctypes.c_int32
+    lib.oracle_philox.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_philox.restype = None
+    return lib
+
+
+class _CProg:
+    """Keeps the numpy buffers alive for the C struct that points at them."""
+
+    def __init__(self, prog: Program):
+        self.W = np.ascontiguousarray(prog.W, dtype=np.int64)
+        self.h = np.ascontiguousarray(prog.h, dtype=np.int64)
+        self.A = np.ascontiguousarray(prog.A, dtype=np.int64)
+        self.b = np.ascontiguousarray(prog.b, dtype=np.int64)
+        self.B = np.ascontiguousarray(np.array(prog.B, dtype=np.int64))
+        self.theta = np.ascontiguousarray(np.array(theta_table(), dtype=np.int32))
+        self.s = _Prog(prog.n_ext, prog.m, prog.T, prog.S,
+                       self.W.ctypes.data, self.h.ctypes.data, self.A.ctypes.data,
+                       self.b.ctypes.data, prog.s_f, prog.s_g, prog.pq,
+                       self.B.ctypes.data, self.theta.ctypes.data,
+                       prog.seed & ((1 << 64) - 1), prog.inst & 0xFFFFFFFF)
+
+
+def philox(ctr, key) -> list:
+    c = np.array(ctr, dtype=np.uint32)
+    k = np.array(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _lib().oracle_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return [int(v) for v in out]
+
+
+def local_field(prog: Program, x, lq, i: int) -> int:
+    cp = _CProg(prog)
+    xb = np.ascontiguousarray(np.array(x, dtype=np.uint8))
+    g = np.ascontiguousarray(residual(prog, xb.astype(np.int64)).astype(np.int64))
+    l = np.ascontiguousarray(np.array(lq, dtype=np.int32))
+    return int(_lib().oracle_local_field(ctypes.byref(cp.s), xb.ctypes.data, g.ctypes.data,
+                                         l.ctypes.data, int(i)))
+
+
+def index_c(prog: Program, Z: int, t: int) -> int:
+    cp = _CProg(prog)
+    return int(_lib().oracle_index(ctypes.byref(cp.s), int(Z), int(t)))
+
+
+def sa_round(prog: Program, lq, k: int, r0: int = 0, nrep: int | None = None,
+             nthreads: int | None = None):
+    """Final states (nrep, n_ext) uint8 and residuals (nrep, m) int64 of replicas
+    r0 .. r0+nrep-1 in round k under multipliers lq."""
+    nrep = prog.R - r0 if nrep is None else int(nrep)
+    nthreads = (os.cpu_count() or 1) if nthreads is None else int(nthreads)
+    cp = _CProg(prog)
+    l = np.ascontiguousarray(np.array(lq, dtype=np.int32).reshape(prog.m))
+    x = np.zeros((nrep, prog.n_ext), dtype=np.uint8)
+    g = np.zeros((nrep, max(prog.m, 1)), dtype=np.int64)
+    rc = _lib().oracle_sa_round(ctypes.byref(cp.s), l.ctypes.data, int(k), int(r0), nrep,
+                                x.ctypes.data, g.ctypes.data, nthreads)
+    if rc != 0:
+        raise RuntimeError("oracle_sa_round failed")
+    return x, g[:, :prog.m]
+
+
+# ---------------------------------------------------------------------------
+# the whole loop
+
+def saim(prob: Problem, par: Params, rounds: int, lq0=None, nthreads: int | None = None,
+         keep_states: bool = True):
+    """Algorithm 1 with R replicas per round.  Returns a dict with per-round
+    multipliers used, per-replica final states / residuals / profits /
+    feasibility, and the best feasible (profit, round, replica, x)."""
+    prog = build_program(prob, par)
+    lq = [0] * prog.m if lq0 is None else [int(v) for v in lq0]
+    lq = [max(-prog.lq_max, min(prog.lq_max, v)) for v in lq]
+    acc = [v << 24 for v in lq]
+    best = None
+    log = []
+    for k in range(rounds):
+        x, g = sa_round(prog, lq, k, 0, prog.R, nthreads)
+        profit, feas = score(prog, x)
+        for r in range(prog.R):
+            if feas[r] and (best is None or int(profit[r]) > best[0]):
+                best = (int(profit[r]), k, r, x[r, :prog.n].copy())
+        G = [int(v) for v in g.sum(axis=0)]
+        entry = {"lq": list(lq), "G": G, "feasible": int(feas.sum())}
+        if keep_states:
+            entry.update(x=x, g=g, profit=profit, feasible_mask=feas)
+        log.append(entry)
+        acc, lq = lambda_step(prog, acc, G)
+    return {"program": prog, "rounds": log, "best": best, "lq": lq, "acc": acc}
