@@ -1,0 +1,189 @@
+/*
+ * pbit.h -- C ABI of the MI355X-native self-adaptive Ising machine (SAIM).
+ *
+ * The library samples the Lagrangian of a constrained binary problem with a
+ * software probabilistic-bit (p-bit) Ising machine on one gfx950 GPU and
+ * adapts the Lagrange multipliers between annealing runs (Delacour,
+ * "Self-Adaptive Ising Machines for Constrained Optimization", Algorithm 1,
+ * Sec. III).
+ *
+ * Conventions shared by every entry point
+ *  - Problems are stated in maximisation form: maximise profit(x) subject to
+ *    weight * x <= capacity, x in {0,1}^n (the paper minimises f = -profit,
+ *    Sec. II Eq. primal_problem; Sec. IV-A and IV-B give the QKP and MKP forms).
+ *  - All settings are in the paper's normalised units (Sec. IV-A: profits are
+ *    divided by max|profit|, constraint data by max(|weight|, |capacity|)).
+ *    Rationals are passed as (numerator, denominator) pairs.
+ *  - Host arrays passed in are read during the call and may be freed after it.
+ *  - All device memory is owned by the caller: the library never allocates
+ *    device memory and never creates streams.  An instance borrows its
+ *    workspace (pbit_workspace_bytes bytes, 256-byte aligned) until
+ *    pbit_destroy_instance.
+ *  - Every call returns a pbit_status; nothing throws or aborts.  On failure
+ *    pbit_last_error() returns a message for the calling thread.  Argument
+ *    and range errors are detected synchronously; asynchronous device errors
+ *    surface at the next call that synchronises (PBIT_EDEVICE), after which the
+ *    instance only accepts pbit_destroy_instance.
+ *  - An instance may be used from one host thread at a time.  Calls on one
+ *    instance must be ordered on one stream (or synchronised by the caller).
+ *  - The library is built for gfx950 only; a call on another device returns
+ *    PBIT_EDEVICE.
+ */
+#ifndef PBIT_H
+#define PBIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *pbit_stream; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+    PBIT_OK = 0,
+    PBIT_NOFEAS = 1,      /* no feasible sample yet: not an error */
+    PBIT_EINVAL = -1,     /* malformed argument */
+    PBIT_ERANGE = -2,     /* instance or settings exceed the exact integer bounds */
+    PBIT_EWORKSPACE = -3, /* workspace missing, too small or misaligned */
+    PBIT_EDEVICE = -4,    /* HIP error, or device is not gfx950 */
+    PBIT_ESTATE = -5      /* instance unusable after a device error */
+} pbit_status;
+
+typedef enum { PBIT_QKP = 0, PBIT_MKP = 1 } pbit_kind;
+
+/* Problem (Sec. IV-A quadratic knapsack, Sec. IV-B multidimensional knapsack).
+ *  QKP: profit is n*n row-major and symmetric; the diagonal holds the item
+ *       values h_i, the off-diagonal the pair values W_ij (each pair counts
+ *       once in the objective); |entries| <= 127.
+ *  MKP: profit is a length-n vector of item values.
+ *  weight is m*n row-major (non-negative), capacity has m entries (non-negative).
+ *  density_num/den is the nominal pair density d used by the penalty rule
+ *  P = alpha d N (Sec. III-A); it is ignored for MKP, whose d is 2/(N+1)
+ *  (Sec. IV-B).  N counts slack spins. */
+typedef struct {
+    int32_t kind;
+    int32_t n, m;
+    const int32_t *profit;
+    const int32_t *weight;
+    const int64_t *capacity;
+    int32_t density_num, density_den;
+} pbit_problem;
+
+/* Sampler settings (Sec. III-B and Table 1).
+ *  replicas     R independent chains per round; they share lambda.
+ *  sweeps       T Monte-Carlo sweeps per annealing run (>= 1).
+ *  beta         beta_max of the linear schedule beta_t = beta_max t/(T-1).
+ *  eta          multiplier step size (Algorithm 1); lambda += eta * mean_r g_r / s_g.
+ *  p_q          256*P directly, or -1 for the rule P = alpha d N.
+ *  alpha        the rule's constant.
+ *  seed         Philox4x32-10 key.
+ *  instance_id  last Philox counter word.
+ *  fixed_beta   nonzero: every sweep runs at beta_max (test mode). */
+typedef struct {
+    int32_t replicas, sweeps;
+    int32_t beta_num, beta_den;
+    int32_t eta_num, eta_den;
+    int32_t p_q;
+    int32_t alpha_num, alpha_den;
+    uint64_t seed;
+    uint32_t instance_id;
+    int32_t fixed_beta;
+} pbit_params;
+
+/* Host-side description of a compiled instance (no device needed). */
+typedef struct {
+    int32_t n, m, n_ext, n_pad;  /* original bits, constraints, spins with slack, padded */
+    int32_t words;               /* 32-bit words per replica state (bits of n_ext spins) */
+    int64_t s_f, s_g;            /* normalisation scales */
+    int64_t p_q;                 /* 256 * P */
+    int32_t shift;               /* beta grid shift S */
+    int32_t lq_max;              /* |lambda_q| bound (lambda on the 2^-8 grid) */
+    int32_t variant;             /* 0 quadratic field kernel, 1 linear, 2 linear with 64-bit dots */
+    int32_t reserved;
+    size_t workspace_bytes;
+    /* layout of the buffer filled by pbit_round_outputs (byte offsets) */
+    size_t out_x, out_g, out_profit, out_feasible, out_G, out_lambda, out_round, out_bytes;
+} pbit_plan_info;
+
+/* Compiles the instance on the host and describes it.  Defines the encoding of
+ * Sec. IV-A (slack bits Q_k = floor(log2 b_k + 1), zero-padded profits) and the
+ * exact integer scales.  Returns PBIT_EINVAL / PBIT_ERANGE as
+ * pbit_create_instance would. */
+pbit_status pbit_plan(const pbit_problem *prob, const pbit_params *par, pbit_plan_info *out);
+
+/* Workspace size in bytes for (prob, par); 0 if the pair is invalid. */
+size_t pbit_workspace_bytes(const pbit_problem *prob, const pbit_params *par);
+
+typedef struct pbit_instance pbit_instance; /* opaque */
+
+/* Uploads the compiled instance into dev_ws (device memory owned by the caller,
+ * 256-byte aligned, at least pbit_workspace_bytes) with copies ordered on
+ * stream, sets lambda = 0 and the round counter to 0 (Algorithm 1 start).
+ * The instance runs on the device that is current at this call.
+ * Errors: PBIT_EINVAL (null or malformed arguments), PBIT_ERANGE (integer
+ * bounds), PBIT_EWORKSPACE (dev_ws null, misaligned or ws_bytes too small),
+ * PBIT_EDEVICE (HIP failure or device not gfx950).  *out is set only on OK. */
+pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *par, void *dev_ws,
+                                 size_t ws_bytes, pbit_stream stream, pbit_instance **out);
+
+/* One annealing run of every replica (Sec. III-B; Algorithm 1 "minimise L_k"):
+ * each replica starts at x = 0 and performs T sequential Gibbs sweeps of the
+ * p-bit update (Eq. Ii_eq, Eq. mi_eq) with beta rising linearly; its last
+ * state is its sample.  The round epilogue then scores every sample on the
+ * original bits (feasible iff weight*x <= capacity, profit per Sec. IV-A),
+ * keeps the best feasible sample over all rounds (largest profit, ties to the
+ * earliest round, then the lowest replica), sums the residuals g = A x - b
+ * over replicas for the multiplier step, and advances the round counter.
+ * Asynchronous on stream. */
+pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream);
+
+/* Multiplier step of Algorithm 1 with the replica mean of the residuals:
+ * lambda_n += eta * (sum_r g_r) / (R s_g), accumulated exactly on a 2^-32 grid
+ * and rounded (half away from zero) to the 2^-8 grid the fields use; the
+ * accumulator saturates at +-lq_max/256.  Uses the sums of the last
+ * pbit_sample_round.  Asynchronous on stream. */
+pbit_status pbit_update_lambda(pbit_instance *inst, pbit_stream stream);
+
+/* Sets lambda_q (m int32 values on the 2^-8 grid, host memory) for the next
+ * round, e.g. a predicted starting point instead of Algorithm 1's lambda_0 = 0.
+ * Values are clamped to +-lq_max.  Copy ordered on stream. */
+pbit_status pbit_set_lambda(pbit_instance *inst, const int32_t *lambda_q, pbit_stream stream);
+
+/* Copies the current lambda_q (m values) to host memory; synchronises stream. */
+pbit_status pbit_get_lambda(pbit_instance *inst, int32_t *lambda_q, pbit_stream stream);
+
+/* Best feasible sample so far: profit, the n original bits (host bytes 0/1),
+ * the round and replica it came from.  Synchronises stream.  Returns
+ * PBIT_NOFEAS (outputs untouched) when no feasible sample exists yet.
+ * Any pointer may be NULL. */
+pbit_status pbit_best_feasible(pbit_instance *inst, int64_t *profit, uint8_t *x, int32_t *round,
+                               int32_t *replica, pbit_stream stream);
+
+/* Copies the last round's per-replica results into dev_out (caller-owned
+ * device memory of at least pbit_plan_info.out_bytes), ordered on stream:
+ *   out_x        uint32 [R][words]  final states, bit i of word i/32 = spin i
+ *   out_g        int32  [R][m]      residuals A_ext x - b
+ *   out_profit   int64  [R]         profit of the original bits
+ *   out_feasible int32  [R]         1 if weight*x <= capacity
+ *   out_G        int64  [m]         sum of residuals over replicas
+ *   out_lambda   int32  [m]         lambda_q in force for the next round
+ *   out_round    int32  [1]         rounds completed */
+pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes, pbit_stream stream);
+
+/* Releases host-side state; the workspace may be reused afterwards.  Does not
+ * synchronise: the caller must not free the workspace while work is queued. */
+pbit_status pbit_destroy_instance(pbit_instance *inst);
+
+/* Thread-local message describing the last failing call on this thread. */
+const char *pbit_last_error(void);
+
+/* Threshold table the sampler uses: theta[j + 2304] = round(2^24 (1 + tanh(j/256))/2),
+ * j = -2304..2304, written to host memory (4609 entries).  Host only. */
+pbit_status pbit_theta_table(int32_t *theta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,265 @@
+"""Python binding of libpbit (include/pbit.h): argument marshalling only.
+
+Every step of the sampling path runs in the library's HIP kernels; torch
+supplies device memory (the instance workspace and output buffers) and the
+stream.  The library must be built (paper_2501_04971_amd.build) before use:
+loading fails loudly if libpbit.so is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from fractions import Fraction
+
+import numpy as np
+
+from .generators import KIND_QKP, Params, Problem
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpbit.so")
+
+PBIT_OK, PBIT_NOFEAS = 0, 1
+PBIT_EINVAL, PBIT_ERANGE, PBIT_EWORKSPACE, PBIT_EDEVICE, PBIT_ESTATE = -1, -2, -3, -4, -5
+THETA_LEN = 4609
+
+
+class PbitError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libpbit status {status}: {message}")
+        self.status = status
+
+
+class pbit_problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("profit", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+                ("capacity", ctypes.c_void_p), ("density_num", ctypes.c_int32),
+                ("density_den", ctypes.c_int32)]
+
+
+class pbit_params(ctypes.Structure):
+    _fields_ = [("replicas", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("beta_num", ctypes.c_int32), ("beta_den", ctypes.c_int32),
+                ("eta_num", ctypes.c_int32), ("eta_den", ctypes.c_int32),
+                ("p_q", ctypes.c_int32), ("alpha_num", ctypes.c_int32),
+                ("alpha_den", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("instance_id", ctypes.c_uint32), ("fixed_beta", ctypes.c_int32)]
+
+
+class pbit_plan_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("n_ext", ctypes.c_int32),
+                ("n_pad", ctypes.c_int32), ("words", ctypes.c_int32),
+                ("s_f", ctypes.c_int64), ("s_g", ctypes.c_int64), ("p_q", ctypes.c_int64),
+                ("shift", ctypes.c_int32), ("lq_max", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t),
+                ("out_x", ctypes.c_size_t), ("out_g", ctypes.c_size_t),
+                ("out_profit", ctypes.c_size_t), ("out_feasible", ctypes.c_size_t),
+                ("out_G", ctypes.c_size_t), ("out_lambda", ctypes.c_size_t),
+                ("out_round", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = {
+    "pbit_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_create_instance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_sample_round": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_update_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_set_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_get_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_best_feasible": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_round_outputs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p]),
+    "pbit_destroy_instance": (ctypes.c_int, [ctypes.c_void_p]),
+    "pbit_last_error": (ctypes.c_char_p, []),
+    "pbit_theta_table": (ctypes.c_int, [ctypes.c_void_p]),
+}
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libpbit.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2501_04971_amd.build first")
+        so = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(so, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = so
+    return _LIB
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise PbitError(status, lib().pbit_last_error().decode())
+    return status
+
+
+def _ratio(v) -> tuple:
+    f = Fraction(v)
+    return int(f.numerator), int(f.denominator)
+
+
+class _Marshalled:
+    """C views of a Problem and Params; keeps the numpy buffers alive."""
+
+    def __init__(self, prob: Problem, par: Params):
+        self.profit = np.ascontiguousarray(np.asarray(prob.profit, dtype=np.int32))
+        self.weight = np.ascontiguousarray(np.asarray(prob.weight, dtype=np.int32))
+        self.capacity = np.ascontiguousarray(np.asarray(prob.capacity, dtype=np.int64))
+        dn, dd = _ratio(prob.density)
+        self.problem = pbit_problem(int(prob.kind), prob.n, prob.m, self.profit.ctypes.data,
+                                    self.weight.ctypes.data, self.capacity.ctypes.data, dn, dd)
+        bn, bd = _ratio(par.beta)
+        en, ed = _ratio(par.eta)
+        an, ad = _ratio(par.alpha)
+        self.params = pbit_params(int(par.replicas), int(par.sweeps), bn, bd, en, ed,
+                                  -1 if par.p_q is None else int(par.p_q), an, ad,
+                                  int(par.seed) & ((1 << 64) - 1),
+                                  int(par.instance_id) & 0xFFFFFFFF, 1 if par.fixed_beta else 0)
+
+
+def pbit_plan(prob: Problem, par: Params) -> pbit_plan_info:
+    mp = _Marshalled(prob, par)
+    info = pbit_plan_info()
+    _check(lib().pbit_plan(ctypes.byref(mp.problem), ctypes.byref(mp.params), ctypes.byref(info)))
+    return info
+
+
+def pbit_workspace_bytes(prob: Problem, par: Params) -> int:
+    mp = _Marshalled(prob, par)
+    return int(lib().pbit_workspace_bytes(ctypes.byref(mp.problem), ctypes.byref(mp.params)))
+
+
+def pbit_theta_table() -> np.ndarray:
+    out = np.zeros(THETA_LEN, dtype=np.int32)
+    _check(lib().pbit_theta_table(out.ctypes.data))
+    return out
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def pbit_create_instance(prob: Problem, par: Params, workspace, stream=None) -> int:
+    """workspace: a uint8 CUDA tensor of at least pbit_workspace_bytes bytes."""
+    mp = _Marshalled(prob, par)
+    handle = ctypes.c_void_p()
+    _check(lib().pbit_create_instance(ctypes.byref(mp.problem), ctypes.byref(mp.params),
+                                      workspace.data_ptr(), workspace.numel(),
+                                      _stream_handle(stream), ctypes.byref(handle)))
+    return int(handle.value)
+
+
+def pbit_sample_round(inst: int, stream=None) -> None:
+    _check(lib().pbit_sample_round(inst, _stream_handle(stream)))
+
+
+def pbit_update_lambda(inst: int, stream=None) -> None:
+    _check(lib().pbit_update_lambda(inst, _stream_handle(stream)))
+
+
+def pbit_set_lambda(inst: int, lambda_q, stream=None) -> None:
+    v = np.ascontiguousarray(np.asarray(lambda_q, dtype=np.int32))
+    _check(lib().pbit_set_lambda(inst, v.ctypes.data, _stream_handle(stream)))
+
+
+def pbit_get_lambda(inst: int, m: int, stream=None) -> np.ndarray:
+    out = np.zeros(m, dtype=np.int32)
+    _check(lib().pbit_get_lambda(inst, out.ctypes.data, _stream_handle(stream)))
+    return out
+
+
+def pbit_best_feasible(inst: int, n: int, stream=None):
+    """(profit, x bytes, round, replica) or None when nothing feasible was found."""
+    profit = ctypes.c_int64()
+    rnd = ctypes.c_int32()
+    rep = ctypes.c_int32()
+    x = np.zeros(n, dtype=np.uint8)
+    st = _check(lib().pbit_best_feasible(inst, ctypes.byref(profit), x.ctypes.data,
+                                         ctypes.byref(rnd), ctypes.byref(rep),
+                                         _stream_handle(stream)))
+    if st == PBIT_NOFEAS:
+        return None
+    return int(profit.value), x, int(rnd.value), int(rep.value)
+
+
+def pbit_round_outputs(inst: int, out, stream=None) -> None:
+    _check(lib().pbit_round_outputs(inst, out.data_ptr(), out.numel(), _stream_handle(stream)))
+
+
+def pbit_destroy_instance(inst: int) -> None:
+    _check(lib().pbit_destroy_instance(inst))
+
+
+class Instance:
+    """One compiled instance with its torch-owned workspace on the current device."""
+
+    def __init__(self, prob: Problem, par: Params, stream=None):
+        import torch
+        self.problem, self.params, self.stream = prob, par, stream
+        self.info = pbit_plan(prob, par)
+        # torch's caching allocator hands out blocks aligned to at least 512 bytes
+        self.workspace = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device="cuda")
+        self.outbuf = torch.empty(int(self.info.out_bytes), dtype=torch.uint8, device="cuda")
+        self.handle = pbit_create_instance(prob, par, self.workspace, stream)
+
+    def sample_round(self):
+        pbit_sample_round(self.handle, self.stream)
+
+    def update_lambda(self):
+        pbit_update_lambda(self.handle, self.stream)
+
+    def set_lambda(self, lambda_q):
+        pbit_set_lambda(self.handle, lambda_q, self.stream)
+
+    def get_lambda(self) -> np.ndarray:
+        return pbit_get_lambda(self.handle, self.info.m, self.stream)
+
+    def best_feasible(self):
+        return pbit_best_feasible(self.handle, self.info.n, self.stream)
+
+    def round_outputs(self) -> dict:
+        """Last round's per-replica results, copied to host numpy arrays."""
+        import torch
+        pbit_round_outputs(self.handle, self.outbuf, self.stream)
+        torch.cuda.current_stream().synchronize() if self.stream is None else self.stream.synchronize()
+        raw = self.outbuf.cpu().numpy()
+        i, R, m, w = self.info, self.params.replicas, self.info.m, self.info.words
+
+        def view(off, dtype, count):
+            return raw[off:off + count * np.dtype(dtype).itemsize].view(dtype)
+
+        return {
+            "x_bits": view(i.out_x, np.uint32, R * w).reshape(R, w).copy(),
+            "g": view(i.out_g, np.int32, R * m).reshape(R, m).copy(),
+            "profit": view(i.out_profit, np.int64, R).copy(),
+            "feasible": view(i.out_feasible, np.int32, R).copy(),
+            "G": view(i.out_G, np.int64, m).copy(),
+            "lambda_q": view(i.out_lambda, np.int32, m).copy(),
+            "round": int(view(i.out_round, np.int32, 1)[0]),
+        }
+
+    def close(self):
+        if self.handle:
+            pbit_destroy_instance(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def unpack_bits(bits: np.ndarray, count: int) -> np.ndarray:
+    """(R, words) uint32 -> (R, count) uint8 with bit i of word i//32 = spin i."""
+    b = np.asarray(bits, dtype=np.uint32)
+    idx = np.arange(count)
+    return ((b[:, idx >> 5] >> (idx & 31).astype(np.uint32)) & 1).astype(np.uint8)

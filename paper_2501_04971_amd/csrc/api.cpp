@@ -1,0 +1,706 @@
+// Host side of libpbit: the instance compiler ("program the Ising machine")
+// and the C ABI declared in include/pbit.h.
+//
+// Encoding (Sec. IV-A and IV-B): each constraint a_k.x <= b_k gets
+// Q_k = floor(log2 b_k + 1) slack bits of weight 2^q so that it reads
+// a_k.x + slack_k - b_k = 0; slack bits carry no profit.  The Lagrangian of
+// Eq. Lagrange_energy (penalty of Eq. penalty_energy) in normalised units,
+//   L_n = -profit/s_f + P_n |g|^2 / s_g^2 + lambda_n . g / s_g,
+// with P_n = Pq/256, lambda_n = lq/256 and D = 256 s_f s_g^2, has the exact
+// integer flip field Z_i = -D (L_n(x_i=1) - L_n(x_i=0))
+//   = 256 s_g^2 (h_i + sum_j W_ij x_j) - 2 s_f Pq a_i.g - s_f s_g a_i.lq
+//     - s_f Pq |a_i|^2 (1 - 2 x_i).
+// Only the first and third terms vary per replica; the rest is folded into
+// per-site constants K0_i (x_i = 0) and K1_i (x_i = 1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pbit.h"
+#include "pbit_types.h"
+
+namespace pbit {
+hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
+hipError_t launch_sweep_linear_a(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
+hipError_t launch_sweep_linear_b(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
+hipError_t launch_sweep_linear_c(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
+hipError_t launch_sweep_linear_d(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
+hipError_t launch_round_reduce(const DevInstance &d, hipStream_t stream);
+hipError_t launch_lambda_update(const DevInstance &d, int mode, const int32_t *values,
+                                hipStream_t stream);
+}  // namespace pbit
+
+using namespace pbit;
+
+namespace {
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+thread_local std::string g_error;
+
+pbit_status fail(pbit_status st, const std::string &msg)
+{
+    g_error = msg;
+    return st;
+}
+
+const i128 kZBudget = (i128)1 << 61;
+const int64_t kLqCap = (int64_t)1 << 24;
+
+// floor(num * 2^s / den) and the remainder, by binary long division.
+u128 shifted_div(u128 num, int s, u128 den, u128 *rem)
+{
+    u128 q = num / den, r = num % den;
+    for (int b = 0; b < s; ++b) {
+        r <<= 1;
+        q <<= 1;
+        if (r >= den) {
+            r -= den;
+            q |= 1;
+        }
+    }
+    *rem = r;
+    return q;
+}
+
+// round(num * 2^s / den) half up, num >= 0.
+u128 round_shifted(u128 num, int s, u128 den)
+{
+    u128 r;
+    u128 q = shifted_div(num, s, den, &r);
+    if (2 * r >= den) q += 1;
+    return q;
+}
+
+int bit_length(int64_t v)
+{
+    int q = 0;
+    while (v > 0) {
+        ++q;
+        v >>= 1;
+    }
+    return q;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Threshold table: round(2^24 / (1 + exp(-2 j / 256))) in 80-bit long double.
+bool make_theta(std::vector<int32_t> &t)
+{
+    t.resize(kThetaLen);
+    for (int j = -kThetaHalf; j <= kThetaHalf; ++j) {
+        const long double v = 16777216.0L / (1.0L + expl(-2.0L * (long double)j / 256.0L));
+        const long double fl = floorl(v);
+        const long double fr = v - fl;
+        if (j != 0 && fabsl(fr - 0.5L) < 1e-9L) return false;  // too close to a tie to trust
+        t[j + kThetaHalf] = (int32_t)fl + (fr > 0.5L ? 1 : 0);
+    }
+    return true;
+}
+
+struct Layout {
+    size_t theta, btab, J, acol, kbase, sa2, b, hprof, slack_off, slack_q;  // constants
+    size_t kconst, lam_acc, lam_q, round_k, G, best, best_x, feas;          // state
+    size_t rx, rg, rprofit, rfeas;                                         // outputs
+    size_t upload_end, total;
+};
+
+struct Plan {
+    int kind = 0, n = 0, m = 0, n_ext = 0, n_pad = 0, words = 0, owords = 0, nb = 0;
+    int variant = 0, T = 0, R = 0, S = 0, nq = 0;
+    int64_t s_f = 1, s_g = 1, pq = 0, lq_max = 0;
+    int32_t sg2 = 0, k2 = 0;
+    int64_t sfsg = 0, eta_num = 0, lam_den = 1;
+    uint64_t seed = 0;
+    uint32_t inst = 0;
+    std::vector<int32_t> theta, btab, acol, hprof, slack_off, slack_q;
+    std::vector<int64_t> kbase, sa2, b;
+    std::vector<int8_t> J;  // n_pad x (n_pad + 16)
+    Layout L{};
+};
+
+pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
+{
+    if (!p || !par) return fail(PBIT_EINVAL, "null problem or params");
+    if (p->kind != PBIT_QKP && p->kind != PBIT_MKP) return fail(PBIT_EINVAL, "unknown problem kind");
+    if (p->n < 1 || p->n > 4096) return fail(PBIT_EINVAL, "n must be in [1, 4096]");
+    if (p->m < 1 || p->m > kMaxM) return fail(PBIT_EINVAL, "m must be in [1, 32]");
+    if (!p->profit || !p->weight || !p->capacity) return fail(PBIT_EINVAL, "null problem array");
+    if (par->replicas < 1 || par->replicas > (1 << 24)) return fail(PBIT_EINVAL, "replicas out of range");
+    if (par->sweeps < 1 || par->sweeps > (1 << 24)) return fail(PBIT_EINVAL, "sweeps out of range");
+    if (par->beta_num < 0 || par->beta_den < 1) return fail(PBIT_EINVAL, "beta must be a non-negative rational");
+    if (par->eta_num < 0 || par->eta_den < 1) return fail(PBIT_EINVAL, "eta must be a non-negative rational");
+    if (par->p_q < -1) return fail(PBIT_EINVAL, "p_q must be -1 or >= 0");
+    if (par->p_q == -1 && (par->alpha_num < 0 || par->alpha_den < 1))
+        return fail(PBIT_EINVAL, "alpha must be a non-negative rational");
+    if (p->kind == PBIT_QKP && par->p_q == -1 && (p->density_num < 0 || p->density_den < 1))
+        return fail(PBIT_EINVAL, "density must be a non-negative rational");
+
+    const int n = p->n, m = p->m;
+    P.kind = p->kind;
+    P.n = n;
+    P.m = m;
+    P.T = par->sweeps;
+    P.R = par->replicas;
+    P.seed = par->seed;
+    P.inst = par->instance_id;
+
+    // item data
+    std::vector<int64_t> h(n, 0);
+    std::vector<int32_t> W;  // n x n, zero diagonal (quadratic only)
+    int64_t s_f = 0;
+    if (p->kind == PBIT_QKP) {
+        W.assign((size_t)n * n, 0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const int32_t v = p->profit[(size_t)i * n + j];
+                if (v != p->profit[(size_t)j * n + i]) return fail(PBIT_EINVAL, "QKP profit matrix is not symmetric");
+                if (v < -127 || v > 127) return fail(PBIT_ERANGE, "QKP profits must lie in [-127, 127]");
+                s_f = std::max<int64_t>(s_f, std::llabs(v));
+                if (i == j) h[i] = v;
+                else W[(size_t)i * n + j] = v;
+            }
+    } else {
+        for (int i = 0; i < n; ++i) {
+            h[i] = p->profit[i];
+            s_f = std::max<int64_t>(s_f, std::llabs(h[i]));
+        }
+    }
+    P.s_f = std::max<int64_t>(s_f, 1);
+
+    int64_t s_g = 0;
+    for (int k = 0; k < m; ++k) {
+        const int64_t bk = p->capacity[k];
+        if (bk < 0 || bk >= ((int64_t)1 << 31)) return fail(PBIT_ERANGE, "capacities must lie in [0, 2^31)");
+        s_g = std::max(s_g, bk);
+        for (int i = 0; i < n; ++i) {
+            const int32_t a = p->weight[(size_t)k * n + i];
+            if (a < 0) return fail(PBIT_EINVAL, "weights must be non-negative");
+            s_g = std::max<int64_t>(s_g, a);
+        }
+    }
+    P.s_g = std::max<int64_t>(s_g, 1);
+
+    // slack extension
+    std::vector<int> Q(m);
+    int n_ext = n;
+    P.slack_off.resize(m);
+    P.slack_q.resize(m);
+    P.b.resize(m);
+    for (int k = 0; k < m; ++k) {
+        Q[k] = bit_length(p->capacity[k]);
+        P.slack_off[k] = n_ext;
+        P.slack_q[k] = Q[k];
+        P.b[k] = p->capacity[k];
+        n_ext += Q[k];
+    }
+    P.n_ext = n_ext;
+    P.words = (n_ext + 31) / 32;
+    P.owords = (n + 31) / 32;
+    P.nq = (n_ext + 3) / 4;
+    if (P.words > kMaxWords) return fail(PBIT_ERANGE, "more than 2048 spins");
+    P.acol.assign((size_t)n_ext * m, 0);
+    for (int k = 0; k < m; ++k) {
+        for (int i = 0; i < n; ++i) P.acol[(size_t)i * m + k] = p->weight[(size_t)k * n + i];
+        for (int q = 0; q < Q[k]; ++q) P.acol[(size_t)(P.slack_off[k] + q) * m + k] = 1 << q;
+    }
+
+    // penalty: 256*P given, or the rule P = alpha d N (N counts slack spins)
+    if (par->p_q >= 0) {
+        P.pq = par->p_q;
+    } else {
+        i128 num, den;
+        if (p->kind == PBIT_QKP) {
+            num = (i128)256 * par->alpha_num * p->density_num * n_ext;
+            den = (i128)par->alpha_den * p->density_den;
+        } else {
+            num = (i128)256 * par->alpha_num * 2 * n_ext;
+            den = (i128)par->alpha_den * (n_ext + 1);
+        }
+        const i128 v = (2 * num + den) / (2 * den);
+        if (v >= ((i128)1 << 40)) return fail(PBIT_ERANGE, "penalty too large");
+        P.pq = (int64_t)v;
+    }
+
+    // bounds of the exact fields: |Z| < 2^62 for every state and |lambda_q| <= lq_max
+    int64_t amax = 0, sqmax = 0, gmax = 0, fmax = 0;
+    std::vector<int64_t> gmk(m);
+    for (int k = 0; k < m; ++k) {
+        int64_t tot = 0;
+        for (int i = 0; i < n_ext; ++i) tot += P.acol[(size_t)i * m + k];
+        gmk[k] = std::max<int64_t>(P.b[k], tot - P.b[k]);
+        gmax = std::max(gmax, gmk[k]);
+    }
+    for (int i = 0; i < n_ext; ++i) {
+        int64_t e = 0, sq = 0;
+        for (int k = 0; k < m; ++k) {
+            const int64_t a = P.acol[(size_t)i * m + k];
+            e += a;
+            sq += a * a;
+        }
+        amax = std::max(amax, e);
+        sqmax = std::max(sqmax, sq);
+        int64_t f = i < n ? std::llabs(h[i]) : 0;
+        if (i < n && !W.empty())
+            for (int j = 0; j < n; ++j) f += std::llabs(W[(size_t)i * n + j]);
+        fmax = std::max(fmax, f);
+    }
+    const i128 sg2 = (i128)P.s_g * P.s_g;
+    const i128 zmax0 = (i128)256 * sg2 * fmax + (i128)P.s_f * P.pq * ((i128)2 * amax * gmax + sqmax);
+    if (zmax0 >= kZBudget) return fail(PBIT_ERANGE, "instance fields exceed the 2^61 budget");
+    if (amax == 0) {
+        P.lq_max = kLqCap;
+    } else {
+        const i128 lq = (kZBudget - zmax0) / ((i128)P.s_f * P.s_g * amax);
+        P.lq_max = (int64_t)std::min<i128>(lq, kLqCap);
+    }
+    if (P.lq_max < 256) return fail(PBIT_ERANGE, "multiplier range below 1.0");
+
+    // kernel variant and its narrower integer paths
+    if (p->kind == PBIT_QKP) {
+        if (m != 1) return fail(PBIT_ERANGE, "quadratic instances take exactly one constraint");
+        if (n_ext > kMaxQuadBlocks * 32) return fail(PBIT_ERANGE, "quadratic instances need n_ext <= 352");
+        if (sg2 >= ((i128)1 << 31)) return fail(PBIT_ERANGE, "quadratic instances need s_g^2 < 2^31");
+        if ((i128)amax * gmax >= ((i128)1 << 31)) return fail(PBIT_ERANGE, "residual products exceed int32");
+        P.variant = kQuad;
+        P.nb = (n_ext + 31) / 32;
+        P.n_pad = P.nb * 32;
+    } else {
+        bool narrow = gmax < ((int64_t)1 << 23);
+        for (int i = 0; i < n && narrow; ++i) {
+            i128 s = 0;
+            for (int k = 0; k < m; ++k) {
+                const int64_t a = P.acol[(size_t)i * m + k];
+                if (a >= ((int64_t)1 << 23)) narrow = false;
+                s += (i128)a * gmk[k];
+            }
+            if (s >= ((i128)1 << 31)) narrow = false;
+        }
+        P.variant = narrow ? kLinear : kLinearWide;
+        P.n_pad = P.words * 32;
+    }
+    const i128 k2 = (i128)2 * P.s_f * P.pq;
+    if (k2 >= ((i128)1 << 31)) return fail(PBIT_ERANGE, "2 s_f Pq must stay below 2^31");
+    P.k2 = (int32_t)k2;
+    P.sg2 = (int32_t)std::min<i128>(sg2, INT32_MAX);
+    P.sfsg = P.s_f * P.s_g;
+
+    // multiplier step: acc += round(2^32 eta_num G / (eta_den R s_g)), G <= R gmax
+    const i128 lam_den = (i128)par->eta_den * P.R * P.s_g;
+    if ((i128)par->eta_num * P.R * gmax >= ((i128)1 << 62) || lam_den >= ((i128)1 << 62))
+        return fail(PBIT_ERANGE, "multiplier step exceeds 64-bit bounds");
+    if (((i128)par->eta_num * gmax << 32) >= ((i128)1 << 62) * par->eta_den * P.s_g)
+        return fail(PBIT_ERANGE, "multiplier step too large");
+    P.eta_num = par->eta_num;
+    P.lam_den = (int64_t)lam_den;
+
+    // beta grid: B_t = round(2^S beta_t / (2 s_f s_g^2)), S the smallest giving B_{T-1} >= 2^30
+    const u128 den = (u128)2 * P.s_f * (u128)sg2;
+    const bool flat = par->fixed_beta || P.T == 1;
+    P.btab.assign(P.T, 0);
+    if (par->beta_num == 0) {
+        P.S = 32;
+    } else {
+        int S = 1;
+        while (round_shifted((u128)par->beta_num, S, den * (u128)par->beta_den) < ((u128)1 << 30)) {
+            if (++S > 94) return fail(PBIT_ERANGE, "beta grid shift out of range");
+        }
+        P.S = S;
+        for (int t = 0; t < P.T; ++t) {
+            u128 v;
+            if (flat) v = round_shifted((u128)par->beta_num, S, den * (u128)par->beta_den);
+            else v = round_shifted((u128)par->beta_num * (u128)t, S, den * (u128)par->beta_den * (u128)(P.T - 1));
+            P.btab[t] = (int32_t)v;
+        }
+    }
+
+    // per-site constants independent of lambda
+    P.kbase.resize(n_ext);
+    P.sa2.resize(n_ext);
+    for (int i = 0; i < n_ext; ++i) {
+        int64_t sq = 0;
+        for (int k = 0; k < m; ++k) {
+            const int64_t a = P.acol[(size_t)i * m + k];
+            sq += a * a;
+        }
+        const i128 Sa = (i128)P.s_f * P.pq * sq;
+        const int64_t hi = i < n ? h[i] : 0;
+        P.kbase[i] = (int64_t)((i128)256 * sg2 * hi - Sa);
+        P.sa2[i] = (int64_t)(2 * Sa);
+    }
+    P.hprof.resize(n);
+    for (int i = 0; i < n; ++i) P.hprof[i] = (int32_t)h[i];
+    if (P.variant == kQuad) {
+        const int ls = P.n_pad + 16;
+        P.J.assign((size_t)P.n_pad * ls, 0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) P.J[(size_t)i * ls + j] = (int8_t)W[(size_t)i * n + j];
+    }
+    if (!make_theta(P.theta)) return fail(PBIT_ERANGE, "threshold table rounding undecidable");
+
+    // workspace layout
+    Layout &L = P.L;
+    size_t o = 0;
+    auto put = [&o](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.theta = put(kThetaLen * 4);
+    L.btab = put((size_t)P.T * 4);
+    L.J = put(P.J.size());
+    L.acol = put(P.acol.size() * 4);
+    L.kbase = put((size_t)n_ext * 8);
+    L.sa2 = put((size_t)n_ext * 8);
+    L.b = put((size_t)m * 8);
+    L.hprof = put((size_t)n * 4);
+    L.slack_off = put((size_t)m * 4);
+    L.slack_q = put((size_t)m * 4);
+    L.lam_acc = put((size_t)m * 8);
+    L.lam_q = put((size_t)m * 4);
+    L.round_k = put(4);
+    L.G = put((size_t)m * 8);
+    L.best = put(4 * 8);
+    L.best_x = put((size_t)P.words * 4);
+    L.feas = put(4);
+    L.upload_end = o;
+    L.kconst = put((size_t)n_ext * 16);
+    L.rx = put((size_t)P.R * P.words * 4);
+    L.rg = put((size_t)P.R * m * 4);
+    L.rprofit = put((size_t)P.R * 8);
+    L.rfeas = put((size_t)P.R * 4);
+    L.total = o;
+    return PBIT_OK;
+}
+
+void fill_plan_info(const Plan &P, pbit_plan_info *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->n = P.n;
+    out->m = P.m;
+    out->n_ext = P.n_ext;
+    out->n_pad = P.n_pad;
+    out->words = P.words;
+    out->s_f = P.s_f;
+    out->s_g = P.s_g;
+    out->p_q = P.pq;
+    out->shift = P.S;
+    out->lq_max = (int32_t)P.lq_max;
+    out->variant = P.variant;
+    out->workspace_bytes = P.L.total;
+    size_t o = 0;
+    auto put = [&o](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    out->out_x = put((size_t)P.R * P.words * 4);
+    out->out_g = put((size_t)P.R * P.m * 4);
+    out->out_profit = put((size_t)P.R * 8);
+    out->out_feasible = put((size_t)P.R * 4);
+    out->out_G = put((size_t)P.m * 8);
+    out->out_lambda = put((size_t)P.m * 4);
+    out->out_round = put(4);
+    out->out_bytes = o;
+}
+
+int waves_per_block(const Plan &P)
+{
+    if (const char *e = std::getenv("PBIT_WAVES_PER_BLOCK")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 4) return v;
+    }
+    const int waves = (P.R + kWave - 1) / kWave;
+    return waves <= 256 ? 1 : 4;
+}
+
+}  // namespace
+
+struct pbit_instance {
+    Plan plan;
+    DevInstance dev{};
+    std::vector<unsigned char> upload;
+    int device = 0;
+    int wpb = 1;
+    bool broken = false;
+};
+
+namespace {
+
+pbit_status device_error(pbit_instance *inst, hipError_t e, const char *what)
+{
+    if (inst) inst->broken = true;
+    return fail(PBIT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+pbit_status check_live(pbit_instance *inst)
+{
+    if (!inst) return fail(PBIT_EINVAL, "null instance");
+    if (inst->broken) return fail(PBIT_ESTATE, "instance is unusable after a device error");
+    return PBIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pbit_last_error(void) { return g_error.c_str(); }
+
+pbit_status pbit_theta_table(int32_t *theta)
+{
+    if (!theta) return fail(PBIT_EINVAL, "null output");
+    std::vector<int32_t> t;
+    if (!make_theta(t)) return fail(PBIT_ERANGE, "threshold table rounding undecidable");
+    std::memcpy(theta, t.data(), t.size() * 4);
+    return PBIT_OK;
+}
+
+pbit_status pbit_plan(const pbit_problem *prob, const pbit_params *par, pbit_plan_info *out)
+{
+    if (!out) return fail(PBIT_EINVAL, "null output");
+    Plan P;
+    const pbit_status st = make_plan(prob, par, P);
+    if (st != PBIT_OK) return st;
+    fill_plan_info(P, out);
+    return PBIT_OK;
+}
+
+size_t pbit_workspace_bytes(const pbit_problem *prob, const pbit_params *par)
+{
+    Plan P;
+    if (make_plan(prob, par, P) != PBIT_OK) return 0;
+    return P.L.total;
+}
+
+pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *par, void *dev_ws,
+                                 size_t ws_bytes, pbit_stream stream, pbit_instance **out)
+{
+    if (!out) return fail(PBIT_EINVAL, "null output handle");
+    pbit_instance *inst = new (std::nothrow) pbit_instance();
+    if (!inst) return fail(PBIT_EINVAL, "host allocation failed");
+    pbit_status st = make_plan(prob, par, inst->plan);
+    if (st != PBIT_OK) {
+        delete inst;
+        return st;
+    }
+    const Plan &P = inst->plan;
+    if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0 || ws_bytes < P.L.total) {
+        delete inst;
+        return fail(PBIT_EWORKSPACE, "workspace missing, misaligned or smaller than pbit_workspace_bytes");
+    }
+    hipError_t e = hipGetDevice(&inst->device);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, inst->device);
+    if (e != hipSuccess) {
+        delete inst;
+        return fail(PBIT_EDEVICE, std::string("device query failed: ") + hipGetErrorString(e));
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        delete inst;
+        return fail(PBIT_EDEVICE, std::string("libpbit is built for gfx950, device is ") + prop.gcnArchName);
+    }
+
+    // host image of constants and initial state
+    const Layout &L = P.L;
+    inst->upload.assign(L.upload_end, 0);
+    unsigned char *img = inst->upload.data();
+    auto cp = [img](size_t off, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(img + off, src, bytes);
+    };
+    cp(L.theta, P.theta.data(), P.theta.size() * 4);
+    cp(L.btab, P.btab.data(), P.btab.size() * 4);
+    cp(L.J, P.J.data(), P.J.size());
+    cp(L.acol, P.acol.data(), P.acol.size() * 4);
+    cp(L.kbase, P.kbase.data(), P.kbase.size() * 8);
+    cp(L.sa2, P.sa2.data(), P.sa2.size() * 8);
+    cp(L.b, P.b.data(), P.b.size() * 8);
+    cp(L.hprof, P.hprof.data(), P.hprof.size() * 4);
+    cp(L.slack_off, P.slack_off.data(), P.slack_off.size() * 4);
+    cp(L.slack_q, P.slack_q.data(), P.slack_q.size() * 4);
+    const int64_t best0[4] = {INT64_MIN, 0, 0, 0};
+    cp(L.best, best0, sizeof(best0));
+
+    unsigned char *base = static_cast<unsigned char *>(dev_ws);
+    DevInstance &d = inst->dev;
+    d.J = reinterpret_cast<const int8_t *>(base + L.J);
+    d.theta = reinterpret_cast<const int32_t *>(base + L.theta);
+    d.Btab = reinterpret_cast<const int32_t *>(base + L.btab);
+    d.acol = reinterpret_cast<const int32_t *>(base + L.acol);
+    d.kbase = reinterpret_cast<const int64_t *>(base + L.kbase);
+    d.sa2 = reinterpret_cast<const int64_t *>(base + L.sa2);
+    d.b = reinterpret_cast<const int64_t *>(base + L.b);
+    d.hprof = reinterpret_cast<const int32_t *>(base + L.hprof);
+    d.slack_off = reinterpret_cast<const int32_t *>(base + L.slack_off);
+    d.slack_q = reinterpret_cast<const int32_t *>(base + L.slack_q);
+    d.kconst = reinterpret_cast<int64_t *>(base + L.kconst);
+    d.lam_acc = reinterpret_cast<int64_t *>(base + L.lam_acc);
+    d.lam_q = reinterpret_cast<int32_t *>(base + L.lam_q);
+    d.round_k = reinterpret_cast<int32_t *>(base + L.round_k);
+    d.G = reinterpret_cast<int64_t *>(base + L.G);
+    d.best = reinterpret_cast<int64_t *>(base + L.best);
+    d.best_x = reinterpret_cast<uint32_t *>(base + L.best_x);
+    d.feas_count = reinterpret_cast<int32_t *>(base + L.feas);
+    d.rx = reinterpret_cast<uint32_t *>(base + L.rx);
+    d.rg = reinterpret_cast<int32_t *>(base + L.rg);
+    d.rprofit = reinterpret_cast<int64_t *>(base + L.rprofit);
+    d.rfeas = reinterpret_cast<int32_t *>(base + L.rfeas);
+    d.n = P.n;
+    d.m = P.m;
+    d.n_ext = P.n_ext;
+    d.n_pad = P.n_pad;
+    d.words = P.words;
+    d.owords = P.owords;
+    d.R = P.R;
+    d.T = P.T;
+    d.S = P.S;
+    d.nq = P.nq;
+    d.sg2 = P.sg2;
+    d.k2 = P.k2;
+    d.sfsg = P.sfsg;
+    d.lq_max = P.lq_max;
+    d.eta_num = P.eta_num;
+    d.lam_den = P.lam_den;
+    d.seed_lo = (uint32_t)P.seed;
+    d.seed_hi = (uint32_t)(P.seed >> 32);
+    d.inst_id = P.inst;
+    inst->wpb = waves_per_block(P);
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    e = hipMemcpyAsync(dev_ws, inst->upload.data(), L.upload_end, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_lambda_update(d, 0, nullptr, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        pbit_status r = device_error(nullptr, e, "instance upload failed");
+        delete inst;
+        return r;
+    }
+    *out = inst;
+    return PBIT_OK;
+}
+
+pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
+{
+    pbit_status st = check_live(inst);
+    if (st != PBIT_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const DevInstance &d = inst->dev;
+    hipError_t e;
+    switch (inst->plan.variant) {
+        case kQuad:
+            e = launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
+            break;
+        default: {
+            const bool wide = inst->plan.variant == kLinearWide;
+            if (d.m <= 6) e = launch_sweep_linear_a(d, wide, inst->wpb, s);
+            else if (d.m <= 12) e = launch_sweep_linear_b(d, wide, inst->wpb, s);
+            else if (d.m <= 20) e = launch_sweep_linear_c(d, wide, inst->wpb, s);
+            else e = launch_sweep_linear_d(d, wide, inst->wpb, s);
+        }
+    }
+    if (e == hipSuccess) e = launch_round_reduce(d, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return device_error(inst, e, "sample_round launch failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_update_lambda(pbit_instance *inst, pbit_stream stream)
+{
+    pbit_status st = check_live(inst);
+    if (st != PBIT_OK) return st;
+    hipError_t e = launch_lambda_update(inst->dev, 1, nullptr, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return device_error(inst, e, "update_lambda launch failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_set_lambda(pbit_instance *inst, const int32_t *lambda_q, pbit_stream stream)
+{
+    pbit_status st = check_live(inst);
+    if (st != PBIT_OK) return st;
+    if (!lambda_q) return fail(PBIT_EINVAL, "null lambda");
+    int32_t v[kMaxM] = {0};
+    const int64_t cap = inst->plan.lq_max;
+    for (int k = 0; k < inst->plan.m; ++k) v[k] = (int32_t)std::max<int64_t>(-cap, std::min<int64_t>(cap, lambda_q[k]));
+    hipError_t e = launch_lambda_update(inst->dev, 2, v, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return device_error(inst, e, "set_lambda launch failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_get_lambda(pbit_instance *inst, int32_t *lambda_q, pbit_stream stream)
+{
+    pbit_status st = check_live(inst);
+    if (st != PBIT_OK) return st;
+    if (!lambda_q) return fail(PBIT_EINVAL, "null output");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(lambda_q, inst->dev.lam_q, (size_t)inst->plan.m * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(inst, e, "get_lambda failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_best_feasible(pbit_instance *inst, int64_t *profit, uint8_t *x, int32_t *round,
+                               int32_t *replica, pbit_stream stream)
+{
+    pbit_status st = check_live(inst);
+    if (st != PBIT_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int64_t best[4];
+    std::vector<uint32_t> bits(inst->plan.words);
+    hipError_t e = hipMemcpyAsync(best, inst->dev.best, sizeof(best), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bits.data(), inst->dev.best_x, bits.size() * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(inst, e, "best_feasible failed");
+    if (best[3] == 0) return PBIT_NOFEAS;
+    if (profit) *profit = best[0];
+    if (round) *round = (int32_t)best[1];
+    if (replica) *replica = (int32_t)best[2];
+    if (x)
+        for (int i = 0; i < inst->plan.n; ++i) x[i] = (uint8_t)((bits[i >> 5] >> (i & 31)) & 1u);
+    return PBIT_OK;
+}
+
+pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes, pbit_stream stream)
+{
+    pbit_status st = check_live(inst);
+    if (st != PBIT_OK) return st;
+    pbit_plan_info info;
+    fill_plan_info(inst->plan, &info);
+    if (!dev_out || bytes < info.out_bytes) return fail(PBIT_EWORKSPACE, "output buffer too small");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char *o = static_cast<unsigned char *>(dev_out);
+    const DevInstance &d = inst->dev;
+    const Plan &P = inst->plan;
+    struct Piece {
+        size_t off;
+        const void *src;
+        size_t bytes;
+    } pieces[] = {
+        {info.out_x, d.rx, (size_t)P.R * P.words * 4}, {info.out_g, d.rg, (size_t)P.R * P.m * 4},
+        {info.out_profit, d.rprofit, (size_t)P.R * 8}, {info.out_feasible, d.rfeas, (size_t)P.R * 4},
+        {info.out_G, d.G, (size_t)P.m * 8},            {info.out_lambda, d.lam_q, (size_t)P.m * 4},
+        {info.out_round, d.round_k, 4},
+    };
+    for (const Piece &pc : pieces) {
+        hipError_t e = hipMemcpyAsync(o + pc.off, pc.src, pc.bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return device_error(inst, e, "round_outputs copy failed");
+    }
+    return PBIT_OK;
+}
+
+pbit_status pbit_destroy_instance(pbit_instance *inst)
+{
+    if (!inst) return fail(PBIT_EINVAL, "null instance");
+    delete inst;
+    return PBIT_OK;
+}
+
+}  // extern "C"

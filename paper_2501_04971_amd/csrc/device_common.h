@@ -1,0 +1,85 @@
+// Device helpers shared by the sampling kernels (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pbit_types.h"
+
+namespace pbit {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 products
+// with the Weyl key schedule.  The counter's third word is the replica, fixed
+// for a lane, so its first-round product m2 = 0xCD9E8D57 * c2 is passed in.
+__device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint64_t m2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+    const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+    uint32_t x0 = (uint32_t)(m2 >> 32) ^ c1 ^ k0;
+    uint32_t x1 = (uint32_t)m2;
+    uint32_t x2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+    uint32_t x3 = (uint32_t)m0;
+#pragma unroll
+    for (int rd = 1; rd < 10; ++rd) {
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = y0;
+        x2 = y2;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+// Threshold index clamp(floor((Z*B + 2^(S-1)) / 2^S), -2304, 2304) for
+// |Z| < 2^62, 0 <= B < 2^31, 1 <= S <= 94, without a 128-bit product:
+// Z*B = zh*B*2^32 + zl*B with zh = Z >> 32 (signed), zl = Z mod 2^32.
+__device__ __forceinline__ int32_t theta_index(int64_t Z, int32_t B, int32_t S)
+{
+    const uint32_t zl = (uint32_t)Z;
+    const int32_t zh = (int32_t)(Z >> 32);
+    const uint64_t lo = (uint64_t)zl * (uint64_t)(uint32_t)B;
+    if (S > 32) {
+        const int32_t sh = S - 32;
+        int64_t hi = (int64_t)zh * (int64_t)B + (int64_t)(lo >> 32) + ((int64_t)1 << (sh - 1));
+        const int64_t lim = (int64_t)kThetaHalf << sh;
+        hi = hi < -lim ? -lim : hi;
+        hi = hi > lim ? lim : hi;
+        return (int32_t)(hi >> sh);
+    }
+    const uint64_t lo2 = lo + ((uint64_t)1 << (S - 1));
+    const int64_t hi = (int64_t)zh * (int64_t)B + (int64_t)(lo2 >> 32);
+    if (hi >= ((int64_t)1 << 20)) return kThetaHalf;
+    if (hi < -((int64_t)1 << 20)) return -kThetaHalf;
+    int64_t q = hi;
+    if (S < 32) q = hi * ((int64_t)1 << (32 - S)) + (int64_t)((uint32_t)lo2 >> S);
+    q = q < -kThetaHalf ? -kThetaHalf : q;
+    q = q > kThetaHalf ? kThetaHalf : q;
+    return (int32_t)q;
+}
+
+// Four 0/1 bytes of a word -> four bits.
+__device__ __forceinline__ uint32_t bytes_to_nibble(uint32_t v)
+{
+    return (v | (v >> 7) | (v >> 14) | (v >> 21)) & 0xFu;
+}
+
+__device__ __forceinline__ void swap_halves(uint32_t &a, uint32_t &b)
+{
+    // lanes 32..63 of a trade places with lanes 0..31 of b
+    auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = s[0];
+    b = s[1];
+}
+
+}  // namespace pbit

@@ -1,0 +1,57 @@
+// Internal types shared by the host side of libpbit and its HIP kernels.
+#pragma once
+#include <stdint.h>
+
+namespace pbit {
+
+// Threshold table over beta*I in [-9, 9] at a 2^-8 step.
+constexpr int kThetaHalf = 2304;
+constexpr int kThetaLen = 2 * kThetaHalf + 1;
+constexpr int kThetaBytes = 18448;          // kThetaLen * 4 rounded up to 16 bytes
+constexpr int kMaxM = 32;                   // constraints per instance
+constexpr int kMaxQuadBlocks = 11;          // quadratic kernel: n_ext <= 352
+constexpr int kMaxWords = 64;               // linear kernel: n_ext <= 2048
+constexpr int kWave = 64;
+
+// Everything a kernel needs about one instance; passed by value.
+struct DevInstance {
+    // constants written once at create
+    const int8_t *J;          // quadratic: [n_pad][n_pad + 16] pair profits, zero diagonal
+    const int32_t *theta;     // [kThetaLen]
+    const int32_t *Btab;      // [T] beta grid
+    const int32_t *acol;      // [n_ext][m] extended constraint coefficients, site-major
+    const int64_t *kbase;     // [n_ext] 256 s_g^2 h_i - Sa_i
+    const int64_t *sa2;       // [n_ext] 2 Sa_i,  Sa_i = s_f Pq |a_i|^2
+    const int64_t *b;         // [m]
+    const int32_t *hprof;     // [n] item profits
+    const int32_t *slack_off; // [m] first slack site of constraint k
+    const int32_t *slack_q;   // [m] slack bits of constraint k
+    // state
+    int64_t *kconst;          // [n_ext][2] K0_i, K1_i = per-site field constants at x_i = 0 / 1
+    int64_t *lam_acc;         // [m] lambda_n on a 2^-32 grid
+    int32_t *lam_q;           // [m] lambda_n on a 2^-8 grid
+    int32_t *round_k;         // [1] rounds completed
+    int64_t *G;               // [m] sum of residuals of the last round
+    int64_t *best;            // [4] profit, round, replica, valid
+    uint32_t *best_x;         // [words]
+    int32_t *feas_count;      // [1] feasible replicas of the last round
+    // per-replica outputs of the last round
+    uint32_t *rx;             // [R][words]
+    int32_t *rg;              // [R][m]
+    int64_t *rprofit;         // [R]
+    int32_t *rfeas;           // [R]
+    // scalars
+    int32_t n, m, n_ext, n_pad, words, owords, R, T, S, nq;
+    int32_t sg2;              // s_g^2 (quadratic kernel; < 2^31)
+    int32_t k2;               // 2 s_f Pq (< 2^31)
+    int64_t sfsg;             // s_f s_g
+    int64_t lq_max;
+    int64_t eta_num;
+    int64_t lam_den;          // eta_den * R * s_g
+    uint32_t seed_lo, seed_hi, inst_id;
+    int32_t pad0;
+};
+
+enum Variant { kQuad = 0, kLinear = 1, kLinearWide = 2 };
+
+}  // namespace pbit

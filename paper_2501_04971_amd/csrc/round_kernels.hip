@@ -1,0 +1,160 @@
+// Per-round bookkeeping on the device, so a round needs no host round trip:
+//  - round_reduce: keep the best feasible sample (Algorithm 1, "store feasible
+//    x_k" and the final argmin), sum the residuals over replicas, advance the
+//    round counter;
+//  - lambda_update: the multiplier step lambda <- lambda + eta g (Algorithm 1)
+//    with the replica mean of g, exact on a 2^-32 accumulator and rounded to
+//    the 2^-8 grid, then refresh the per-site field constants that depend on
+//    lambda.
+#include <hip/hip_runtime.h>
+
+#include "pbit_types.h"
+
+namespace pbit {
+
+constexpr int kReduceThreads = 256;
+
+__device__ __forceinline__ bool better(int64_t p, int32_t r, int64_t q, int32_t s)
+{
+    return p > q || (p == q && r < s);
+}
+
+__global__ __launch_bounds__(kReduceThreads) void round_reduce(const DevInstance d)
+{
+    __shared__ int64_t sp[kReduceThreads];
+    __shared__ int32_t sr[kReduceThreads];
+    __shared__ int64_t sg[kReduceThreads];
+    __shared__ int32_t sf[kReduceThreads];
+    const int tid = threadIdx.x;
+
+    int64_t bp = INT64_MIN;
+    int32_t br = INT32_MAX;
+    int32_t nf = 0;
+    for (int r = tid; r < d.R; r += kReduceThreads) {
+        if (d.rfeas[r]) {
+            ++nf;
+            const int64_t p = d.rprofit[r];
+            if (better(p, r, bp, br)) {
+                bp = p;
+                br = r;
+            }
+        }
+    }
+    sp[tid] = bp;
+    sr[tid] = br;
+    sf[tid] = nf;
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+            if (better(sp[tid + h], sr[tid + h], sp[tid], sr[tid])) {
+                sp[tid] = sp[tid + h];
+                sr[tid] = sr[tid + h];
+            }
+            sf[tid] += sf[tid + h];
+        }
+        __syncthreads();
+    }
+    const int32_t k = d.round_k[0];
+    const bool improve = sr[0] != INT32_MAX && (d.best[3] == 0 || sp[0] > d.best[0]);
+    const int32_t rbest = sr[0];
+    if (improve) {
+        for (int w = tid; w < d.words; w += kReduceThreads)
+            d.best_x[w] = d.rx[(int64_t)rbest * d.words + w];
+    }
+    // residual sums, one constraint at a time
+    for (int c = 0; c < d.m; ++c) {
+        int64_t s = 0;
+        for (int r = tid; r < d.R; r += kReduceThreads) s += d.rg[(int64_t)r * d.m + c];
+        sg[tid] = s;
+        __syncthreads();
+        for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+            if (tid < h) sg[tid] += sg[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) d.G[c] = sg[0];
+        __syncthreads();
+    }
+    __syncthreads();  // every thread has read d.best before it is rewritten
+    if (tid == 0) {
+        if (improve) {
+            d.best[0] = sp[0];
+            d.best[1] = k;
+            d.best[2] = rbest;
+            d.best[3] = 1;
+        }
+        d.feas_count[0] = sf[0];
+        d.round_k[0] = k + 1;
+    }
+}
+
+// round(num * 2^32 / den) half away from zero, |num| < 2^62, 0 < den < 2^62,
+// result below 2^62 in magnitude (bounded when the instance is created).
+__device__ int64_t round_scaled_div(int64_t num, int64_t den)
+{
+    const bool neg = num < 0;
+    const uint64_t a = neg ? (uint64_t)(-num) : (uint64_t)num;
+    const uint64_t dv = (uint64_t)den;
+    uint64_t q = a / dv, rem = a % dv;
+    for (int bit = 0; bit < 32; ++bit) {
+        rem <<= 1;
+        q <<= 1;
+        if (rem >= dv) {
+            rem -= dv;
+            q |= 1u;
+        }
+    }
+    if (2 * rem >= dv) q += 1;
+    return neg ? -(int64_t)q : (int64_t)q;
+}
+
+struct LambdaSet {
+    int32_t v[kMaxM];
+};
+
+// mode 0: refresh constants only; 1: multiplier step from d.G; 2: set lambda_q from `set`.
+__global__ __launch_bounds__(256) void lambda_update(const DevInstance d, int mode, LambdaSet set)
+{
+    __shared__ int32_t lq[kMaxM];
+    const int tid = threadIdx.x;
+    if (tid < d.m) {
+        int64_t acc = d.lam_acc[tid];
+        const int64_t cap = d.lq_max << 24;
+        if (mode == 1) acc += round_scaled_div(d.eta_num * d.G[tid], d.lam_den);
+        if (mode == 2) acc = (int64_t)set.v[tid] * (1 << 24);
+        acc = acc > cap ? cap : acc;
+        acc = acc < -cap ? -cap : acc;
+        const int32_t q = acc >= 0 ? (int32_t)((acc + (1 << 23)) >> 24)
+                                   : -(int32_t)((-acc + (1 << 23)) >> 24);
+        d.lam_acc[tid] = acc;
+        d.lam_q[tid] = q;
+        lq[tid] = q;
+    }
+    __syncthreads();
+    for (int i = tid; i < d.n_ext; i += blockDim.x) {
+        int64_t al = 0;
+        for (int c = 0; c < d.m; ++c) al += (int64_t)d.acol[(int64_t)i * d.m + c] * lq[c];
+        const int64_t K0 = d.kbase[i] - d.sfsg * al;
+        d.kconst[2 * i] = K0;
+        d.kconst[2 * i + 1] = K0 + d.sa2[i];
+    }
+}
+
+hipError_t launch_round_reduce(const DevInstance &d, hipStream_t stream)
+{
+    void *args[] = {const_cast<DevInstance *>(&d)};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&round_reduce), dim3(1),
+                           dim3(kReduceThreads), args, 0, stream);
+}
+
+hipError_t launch_lambda_update(const DevInstance &d, int mode, const int32_t *values,
+                                hipStream_t stream)
+{
+    LambdaSet set{};
+    if (values)
+        for (int c = 0; c < d.m && c < kMaxM; ++c) set.v[c] = values[c];
+    void *args[] = {const_cast<DevInstance *>(&d), &mode, &set};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&lambda_update), dim3(1), dim3(256), args,
+                           0, stream);
+}
+
+}  // namespace pbit

@@ -1,0 +1,107 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+entry point, compiles instances to the same integers as the oracle, and
+rejects malformed input with the documented status codes.  No GPU calls."""
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2501_04971_amd import binding as B
+from paper_2501_04971_amd import build as BUILD
+from paper_2501_04971_amd import generators as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(BUILD.LIB):
+        BUILD.build()
+    return B.lib()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pbit.h")).read()
+    return sorted(set(re.findall(r"\b(pbit_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in B.EXPORTS, name
+
+
+def _cases():
+    out = [G.workload(0, 0), G.workload(0, 5), G.workload(1, 0), G.workload(2, 0)]
+    out += [G.workload(3, i) for i in range(6)]
+    prob = G.tiny(7, 2, False, G.rng_for(910, 0))
+    out.append((prob, G.Params(replicas=10, sweeps=7, beta=Fraction(3, 2), p_q=300), 1))
+    prob = G.tiny(9, 1, True, G.rng_for(910, 1))
+    out.append((prob, G.Params(replicas=3, sweeps=1, beta=Fraction(2), fixed_beta=True), 1))
+    return out
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_plan_matches_oracle_program(lib, case):
+    prob, par, _ = _cases()[case]
+    info = B.pbit_plan(prob, par)
+    prog = O.build_program(prob, par)
+    assert info.n_ext == prog.n_ext
+    assert info.s_f == prog.s_f and info.s_g == prog.s_g
+    assert info.p_q == prog.pq
+    assert info.shift == prog.S
+    assert info.lq_max == prog.lq_max
+    assert info.workspace_bytes == B.pbit_workspace_bytes(prob, par) > 0
+    assert info.words == (prog.n_ext + 31) // 32
+    assert info.variant == (0 if prob.kind == G.KIND_QKP else info.variant)
+
+
+def test_theta_table_matches_oracle(lib):
+    assert B.pbit_theta_table().tolist() == list(O.theta_table())
+
+
+def _expect(status, prob, par):
+    with pytest.raises(B.PbitError) as ei:
+        B.pbit_plan(prob, par)
+    assert ei.value.status == status
+    assert B.pbit_workspace_bytes(prob, par) == 0
+
+
+def test_error_codes(lib):
+    prob, par, _ = G.workload(0, 0)
+    bad = G.Problem(7, prob.profit, prob.weight, prob.capacity, prob.density)
+    _expect(B.PBIT_EINVAL, bad, par)
+    asym = np.array(prob.profit)
+    asym[0, 1] += 1
+    _expect(B.PBIT_EINVAL, G.Problem(G.KIND_QKP, asym, prob.weight, prob.capacity, prob.density), par)
+    neg = np.array(prob.weight)
+    neg[0, 3] = -1
+    _expect(B.PBIT_EINVAL, G.Problem(G.KIND_QKP, prob.profit, neg, prob.capacity, prob.density), par)
+    big = np.array(prob.profit)
+    big[2, 2] = 200
+    _expect(B.PBIT_ERANGE, G.Problem(G.KIND_QKP, big, prob.weight, prob.capacity, prob.density), par)
+    two = G.Problem(G.KIND_QKP, prob.profit, np.vstack([prob.weight, prob.weight]),
+                    np.concatenate([prob.capacity, prob.capacity]), prob.density)
+    _expect(B.PBIT_ERANGE, two, par)
+    wide = G.qkp(345, Fraction(1, 2), G.rng_for(911, 0))
+    _expect(B.PBIT_ERANGE, wide, par)
+    _expect(B.PBIT_EINVAL, prob, G.Params(replicas=0))
+    _expect(B.PBIT_EINVAL, prob, G.Params(sweeps=0))
+    _expect(B.PBIT_EINVAL, prob, G.Params(eta=Fraction(-1)))
+
+
+def test_null_workspace_is_rejected_before_any_device_call(lib):
+    prob, par, _ = G.workload(0, 0)
+    mp = B._Marshalled(prob, par)
+    h = ctypes.c_void_p()
+    st = lib.pbit_create_instance(ctypes.byref(mp.problem), ctypes.byref(mp.params), None, 0, None,
+                                  ctypes.byref(h))
+    assert st == B.PBIT_EWORKSPACE and h.value is None
+    assert lib.pbit_sample_round(None, None) == B.PBIT_EINVAL
+    assert b"null instance" in lib.pbit_last_error()

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP sampling path against the CPU oracle, bit for bit.
+
+Every quantity is an integer (states, residuals, profits, multipliers), so the
+bar is exact equality.  Small cases run the whole loop in both; full-size
+workloads are checked on sampled replicas of the first round (lambda = 0 is
+known without running the rest), plus the residual sums and the multiplier
+step as properties of the GPU's own outputs."""
+import os
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2501_04971_amd import binding as B
+from paper_2501_04971_amd import generators as G
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_loop(prob, par, rounds, lq0=None):
+    inst = B.Instance(prob, par)
+    if lq0 is not None:
+        inst.set_lambda(lq0)
+    log = []
+    for _ in range(rounds):
+        lam = inst.get_lambda()
+        inst.sample_round()
+        out = inst.round_outputs()
+        inst.update_lambda()
+        out["lq"] = lam
+        log.append(out)
+    best = inst.best_feasible()
+    lam = inst.get_lambda()
+    inst.close()
+    return log, best, lam
+
+
+def assert_round_equal(prog, ref, got, k):
+    assert [int(v) for v in got["lq"]] == ref["lq"], f"round {k}: multipliers differ"
+    x = B.unpack_bits(got["x_bits"], prog.n_ext)
+    bad = np.nonzero((x != ref["x"]).any(axis=1))[0]
+    assert bad.size == 0, (f"round {k}: {bad.size} replicas differ, first r={bad[0]}, "
+                           f"sites {np.nonzero(x[bad[0]] != ref['x'][bad[0]])[0][:10]}")
+    assert (got["g"] == ref["g"]).all(), f"round {k}: residuals differ"
+    assert (got["profit"] == ref["profit"]).all(), f"round {k}: profits differ"
+    assert (got["feasible"].astype(bool) == ref["feasible_mask"]).all(), f"round {k}: feasibility differs"
+    assert [int(v) for v in got["G"]] == ref["G"], f"round {k}: residual sums differ"
+    assert got["round"] == k + 1
+
+
+def run_parity(prob, par, rounds, lq0=None, label=""):
+    say(f"[parity] {label} n={prob.n} m={prob.m} R={par.replicas} T={par.sweeps} K={rounds}")
+    ref = O.saim(prob, par, rounds, lq0=lq0, nthreads=NTHREADS)
+    log, best, lam = gpu_loop(prob, par, rounds, lq0)
+    prog = ref["program"]
+    for k in range(rounds):
+        assert_round_equal(prog, ref["rounds"][k], log[k], k)
+    assert [int(v) for v in lam] == ref["lq"]
+    if ref["best"] is None:
+        assert best is None
+    else:
+        assert best is not None
+        assert best[0] == ref["best"][0] and best[2] == ref["best"][1] and best[3] == ref["best"][2]
+        assert (best[1] == ref["best"][3]).all()
+    return ref, log
+
+
+def test_workload0_qkp_first_rounds(need_gpu):
+    prob, par, _ = G.workload(0, 0)
+    run_parity(prob, par, 4, label="QKP N=100 d=0.25 (workload 0)")
+
+
+def test_qkp_table1_settings_multiplier_moves(need_gpu):
+    """QKP with Table 1's beta_max = 10 and eta = 20: lambda moves every round."""
+    prob = G.family0(3)
+    par = G.Params(replicas=64, sweeps=300, beta=Fraction(10), eta=Fraction(20))
+    ref, _ = run_parity(prob, par, 6, label="QKP Table-1 settings")
+    assert ref["rounds"][-1]["lq"] != ref["rounds"][0]["lq"]
+
+
+@pytest.mark.parametrize("n,d,R", [(5, Fraction(1, 2), 64), (20, Fraction(1), 100),
+                                   (97, Fraction(3, 4), 130), (330, Fraction(1, 4), 64)])
+def test_qkp_ragged_shapes(need_gpu, n, d, R):
+    """Partial site blocks, phantom lanes (R not a multiple of 64), one to eleven blocks."""
+    prob = G.qkp(n, d, G.rng_for(920, n))
+    par = G.Params(replicas=R, sweeps=40, beta=Fraction(4), eta=Fraction(2))
+    run_parity(prob, par, 3, label=f"QKP ragged n={n}")
+
+
+def test_workload1_mkp_first_rounds(need_gpu):
+    prob, _, _ = G.workload(1, 0)
+    par = G.Params(replicas=128, sweeps=60, beta=Fraction(50), eta=Fraction(1, 20), alpha=Fraction(5))
+    run_parity(prob, par, 3, label="MKP N=250 M=10 (workload 1 generator)")
+
+
+@pytest.mark.parametrize("n,m", [(40, 1), (100, 5), (100, 30), (500, 5)])
+def test_mkp_constraint_counts(need_gpu, n, m):
+    prob = G.mkp(n, m, G.rng_for(921, n * 100 + m))
+    par = G.Params(replicas=70, sweeps=25, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
+    info = B.pbit_plan(prob, par)
+    say(f"variant {info.variant}")
+    run_parity(prob, par, 3, label=f"MKP n={n} m={m}")
+
+
+def test_mkp_wide_dot_path(need_gpu):
+    """Weights large enough that a_i.g leaves int32 select the 64-bit dot variant."""
+    rng = G.rng_for(922, 0)
+    a = rng.integers(1, 20000, size=(8, 200), dtype=np.int64)
+    b = a.sum(axis=1) // 4
+    c = rng.integers(1, 200, size=200)
+    prob = G.Problem(G.KIND_MKP, c.astype(np.int32), a.astype(np.int32), b.astype(np.int64))
+    par = G.Params(replicas=64, sweeps=20, beta=Fraction(30), eta=Fraction(1, 5), alpha=Fraction(5))
+    assert B.pbit_plan(prob, par).variant == 2
+    run_parity(prob, par, 2, label="MKP wide")
+
+
+def test_fixed_beta_and_zero_beta(need_gpu):
+    prob = G.family0(1)
+    run_parity(prob, G.Params(replicas=64, sweeps=20, beta=Fraction(3), fixed_beta=True), 2,
+               label="fixed beta")
+    run_parity(prob, G.Params(replicas=64, sweeps=5, beta=Fraction(0)), 2, label="beta 0")
+
+
+def test_start_from_given_multipliers(need_gpu):
+    """Algorithm 1 started from a chosen lambda_0 (what a predictor would supply)."""
+    prob = G.family0(2)
+    par = G.Params(replicas=64, sweeps=100, beta=Fraction(5), eta=Fraction(3))
+    run_parity(prob, par, 3, lq0=[25600], label="lambda_0 = 100")
+    prob = G.mkp(60, 3, G.rng_for(923, 0))
+    par = G.Params(replicas=64, sweeps=50, beta=Fraction(20), eta=Fraction(1, 4), alpha=Fraction(5))
+    run_parity(prob, par, 2, lq0=[512, -300, 77], label="MKP lambda_0")
+
+
+def _spot_check_round0(prob, par, sample):
+    inst = B.Instance(prob, par)
+    inst.sample_round()
+    out = inst.round_outputs()
+    inst.update_lambda()
+    lam1 = inst.get_lambda()
+    inst.close()
+    prog = O.build_program(prob, par)
+    x = B.unpack_bits(out["x_bits"], prog.n_ext)
+    for r in sample:
+        xo, go = O.sa_round(prog, [0] * prog.m, 0, int(r), 1, 1)
+        assert (x[r] == xo[0]).all(), f"replica {r} state differs"
+        assert (out["g"][r] == go[0]).all(), f"replica {r} residual differs"
+        pr, fe = O.score(prog, xo)
+        assert out["profit"][r] == pr[0] and bool(out["feasible"][r]) == bool(fe[0])
+    # properties over all replicas
+    assert (O.residual(prog, x) == out["g"]).all()
+    pr, fe = O.score(prog, x)
+    assert (pr == out["profit"]).all() and (fe == out["feasible"].astype(bool)).all()
+    assert [int(v) for v in out["G"]] == [int(v) for v in out["g"].astype(np.int64).sum(axis=0)]
+    _, lq = O.lambda_step(prog, [0] * prog.m, [int(v) for v in out["G"]])
+    assert [int(v) for v in lam1] == lq
+
+
+def test_full_size_workload2_round0(need_gpu):
+    """QKP N=300 d=1, 4096 replicas x 5000 sweeps: sampled replicas replayed by the oracle."""
+    prob, par, _ = G.workload(2, 0)
+    say("[parity] workload 2 full size, round 0")
+    _spot_check_round0(prob, par, [0, 1, 63, 64, 2047, 4095])
+
+
+def test_full_size_workload1_round0(need_gpu):
+    """MKP N=250 M=10, 1024 replicas x 2000 sweeps: sampled replicas replayed by the oracle."""
+    prob, par, _ = G.workload(1, 0)
+    say("[parity] workload 1 full size, round 0")
+    _spot_check_round0(prob, par, [0, 5, 511, 1023])
