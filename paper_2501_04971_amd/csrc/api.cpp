@@ -26,7 +26,8 @@
 #include "pbit_types.h"
 
 namespace pbit {
-hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
+hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, bool lookahead,
+                             hipStream_t stream);
 hipError_t launch_sweep_linear_a(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
 hipError_t launch_sweep_linear_b(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
 hipError_t launch_sweep_linear_c(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
@@ -107,7 +108,7 @@ bool make_theta(std::vector<int32_t> &t)
 
 struct Layout {
     size_t theta, btab, J, acol, kbase, sa2, b, hprof, slack_off, slack_q;  // constants
-    size_t kconst, lam_acc, lam_q, round_k, G, best, best_x, feas;          // state
+    size_t kconst /* per-site records */, lam_acc, lam_q, round_k, G, best, best_x, feas;          // state
     size_t rx, rg, rprofit, rfeas;                                         // outputs
     size_t upload_end, total;
 };
@@ -116,8 +117,12 @@ struct Plan {
     int kind = 0, n = 0, m = 0, n_ext = 0, n_pad = 0, words = 0, owords = 0, nb = 0;
     int variant = 0, T = 0, R = 0, S = 0, nq = 0;
     int64_t s_f = 1, s_g = 1, pq = 0, lq_max = 0;
-    int32_t sg2 = 0, k2 = 0;
+    int32_t sg2 = 0, k2 = 0;       // scaled by 2^u
+    int32_t zsh = 0, ish = 0, hclo = 0, hchi = 0;
+    int64_t irnd = 0;
     int64_t sfsg = 0, eta_num = 0, lam_den = 1;
+    int n_rec = 0;                 // per-site records (padding included)
+    std::vector<int64_t> site;     // [n_rec][4]: K0, K1 (filled on the device), c, meta
     uint64_t seed = 0;
     uint32_t inst = 0;
     std::vector<int32_t> theta, btab, acol, hprof, slack_off, slack_q;
@@ -206,7 +211,8 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     P.owords = (n + 31) / 32;
     P.nq = (n_ext + 3) / 4;
     if (P.words > kMaxWords) return fail(PBIT_ERANGE, "more than 2048 spins");
-    P.acol.assign((size_t)n_ext * m, 0);
+    P.n_rec = P.words * 32 + 32;
+    P.acol.assign((size_t)P.n_rec * m, 0);
     for (int k = 0; k < m; ++k) {
         for (int i = 0; i < n; ++i) P.acol[(size_t)i * m + k] = p->weight[(size_t)k * n + i];
         for (int q = 0; q < Q[k]; ++q) P.acol[(size_t)(P.slack_off[k] + q) * m + k] = 1 << q;
@@ -268,7 +274,8 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
         if (m != 1) return fail(PBIT_ERANGE, "quadratic instances take exactly one constraint");
         if (n_ext > kMaxQuadBlocks * 32) return fail(PBIT_ERANGE, "quadratic instances need n_ext <= 352");
         if (sg2 >= ((i128)1 << 31)) return fail(PBIT_ERANGE, "quadratic instances need s_g^2 < 2^31");
-        if ((i128)amax * gmax >= ((i128)1 << 31)) return fail(PBIT_ERANGE, "residual products exceed int32");
+        if ((i128)amax * gmax >= ((i128)1 << 31) || amax >= (1 << 23) || gmax >= (1 << 23))
+            return fail(PBIT_ERANGE, "residual products exceed the 24-bit multiply path");
         P.variant = kQuad;
         P.nb = (n_ext + 31) / 32;
         P.n_pad = P.nb * 32;
@@ -287,9 +294,6 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
         P.n_pad = P.words * 32;
     }
     const i128 k2 = (i128)2 * P.s_f * P.pq;
-    if (k2 >= ((i128)1 << 31)) return fail(PBIT_ERANGE, "2 s_f Pq must stay below 2^31");
-    P.k2 = (int32_t)k2;
-    P.sg2 = (int32_t)std::min<i128>(sg2, INT32_MAX);
     P.sfsg = P.s_f * P.s_g;
 
     // multiplier step: acc += round(2^32 eta_num G / (eta_den R s_g)), G <= R gmax
@@ -319,6 +323,54 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
             else v = round_shifted((u128)par->beta_num * (u128)t, S, den * (u128)par->beta_den * (u128)(P.T - 1));
             P.btab[t] = (int32_t)v;
         }
+    }
+
+    // The kernels carry 2^u Z with S + u >= 34 so that the index needs one
+    // 64-bit shift (see theta_index); u > 0 only for instances of tiny scale.
+    const int zsh = P.S >= 34 ? 0 : 34 - P.S;
+    const i128 zfull = zmax0 + (i128)P.s_f * P.s_g * amax * P.lq_max;
+    if ((zfull << zsh) >= ((i128)1 << 62)) return fail(PBIT_ERANGE, "scaled fields exceed 2^62");
+    if ((k2 << zsh) >= ((i128)1 << 31)) return fail(PBIT_ERANGE, "2 s_f Pq must stay below 2^31");
+    if (P.variant == kQuad && (sg2 << zsh) >= ((i128)1 << 31))
+        return fail(PBIT_ERANGE, "quadratic instances need s_g^2 < 2^31");
+    P.zsh = zsh;
+    P.k2 = (int32_t)(k2 << zsh);
+    P.sg2 = (int32_t)std::min<i128>(sg2 << zsh, INT32_MAX);
+    P.ish = P.S + zsh - 32;
+    P.irnd = (int64_t)1 << (P.S + zsh - 33);
+    if (P.ish <= 31) {
+        P.hclo = -(int32_t)(1u << (P.ish - 1));
+        P.hchi = (int32_t)((1u << (P.ish - 1)) - 1u);
+    } else {
+        P.hclo = INT32_MIN;
+        P.hchi = INT32_MAX;
+    }
+
+    // per-site records: c_i = change of Z_i when the preceding visit (site i-1)
+    // goes 0 -> 1; meta = (a_i, -1 for a site the loop visits, 0 for padding)
+    P.site.assign((size_t)P.n_rec * 4, 0);
+    for (int i = 1; i < n_ext; ++i) {
+        const bool quad = P.variant == kQuad;
+        bool chained;
+        if (quad) chained = (i % 32) != 0;
+        else if (i < n) chained = (i % 32) != 0;
+        else {
+            // slack bit q >= 1 of the same constraint
+            int k = 0;
+            while (k + 1 < m && i >= P.slack_off[k + 1]) ++k;
+            chained = i > P.slack_off[k] && i < P.slack_off[k] + P.slack_q[k];
+        }
+        if (!chained) continue;
+        i128 aa = 0;
+        for (int k = 0; k < m; ++k) aa += (i128)P.acol[(size_t)i * m + k] * P.acol[(size_t)(i - 1) * m + k];
+        i128 c = -k2 * aa;
+        if (quad && i < n && i - 1 < n) c += (i128)256 * sg2 * W[(size_t)i * n + (i - 1)];
+        P.site[(size_t)i * 4 + 2] = (int64_t)(c << zsh);
+    }
+    for (int i = 0; i < P.n_rec; ++i) {
+        const bool visited = P.variant == kQuad ? i < n_ext : i < n;
+        const int32_t a = (P.variant == kQuad && i < n_ext) ? P.acol[(size_t)i * m] : 0;
+        P.site[(size_t)i * 4 + 3] = (int64_t)(((uint64_t)(visited ? 0xFFFFFFFFu : 0u) << 32) | (uint32_t)a);
     }
 
     // per-site constants independent of lambda
@@ -370,8 +422,8 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     L.best = put(4 * 8);
     L.best_x = put((size_t)P.words * 4);
     L.feas = put(4);
+    L.kconst = put((size_t)P.n_rec * 32);
     L.upload_end = o;
-    L.kconst = put((size_t)n_ext * 16);
     L.rx = put((size_t)P.R * P.words * 4);
     L.rg = put((size_t)P.R * m * 4);
     L.rprofit = put((size_t)P.R * 8);
@@ -429,6 +481,7 @@ struct pbit_instance {
     std::vector<unsigned char> upload;
     int device = 0;
     int wpb = 1;
+    bool lookahead = false;
     bool broken = false;
 };
 
@@ -524,6 +577,7 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
     cp(L.hprof, P.hprof.data(), P.hprof.size() * 4);
     cp(L.slack_off, P.slack_off.data(), P.slack_off.size() * 4);
     cp(L.slack_q, P.slack_q.data(), P.slack_q.size() * 4);
+    cp(L.kconst, P.site.data(), P.site.size() * 8);
     const int64_t best0[4] = {INT64_MIN, 0, 0, 0};
     cp(L.best, best0, sizeof(best0));
 
@@ -539,7 +593,7 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
     d.hprof = reinterpret_cast<const int32_t *>(base + L.hprof);
     d.slack_off = reinterpret_cast<const int32_t *>(base + L.slack_off);
     d.slack_q = reinterpret_cast<const int32_t *>(base + L.slack_q);
-    d.kconst = reinterpret_cast<int64_t *>(base + L.kconst);
+    d.site = reinterpret_cast<int64_t *>(base + L.kconst);
     d.lam_acc = reinterpret_cast<int64_t *>(base + L.lam_acc);
     d.lam_q = reinterpret_cast<int32_t *>(base + L.lam_q);
     d.round_k = reinterpret_cast<int32_t *>(base + L.round_k);
@@ -563,6 +617,11 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
     d.nq = P.nq;
     d.sg2 = P.sg2;
     d.k2 = P.k2;
+    d.zsh = P.zsh;
+    d.ish = P.ish;
+    d.irnd = P.irnd;
+    d.hclo = P.hclo;
+    d.hchi = P.hchi;
     d.sfsg = P.sfsg;
     d.lq_max = P.lq_max;
     d.eta_num = P.eta_num;
@@ -571,6 +630,7 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
     d.seed_hi = (uint32_t)(P.seed >> 32);
     d.inst_id = P.inst;
     inst->wpb = waves_per_block(P);
+    if (const char *e = std::getenv("PBIT_LOOKAHEAD")) inst->lookahead = std::atoi(e) != 0;
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     e = hipMemcpyAsync(dev_ws, inst->upload.data(), L.upload_end, hipMemcpyHostToDevice, s);
@@ -594,7 +654,7 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
     hipError_t e;
     switch (inst->plan.variant) {
         case kQuad:
-            e = launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
+            e = launch_sweep_quad(d, inst->plan.nb, inst->wpb, inst->lookahead, s);
             break;
         default: {
             const bool wide = inst->plan.variant == kLinearWide;

@@ -41,31 +41,36 @@ __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint64_t 
     out[3] = x3;
 }
 
-// Threshold index clamp(floor((Z*B + 2^(S-1)) / 2^S), -2304, 2304) for
-// |Z| < 2^62, 0 <= B < 2^31, 1 <= S <= 94, without a 128-bit product:
-// Z*B = zh*B*2^32 + zl*B with zh = Z >> 32 (signed), zl = Z mod 2^32.
-__device__ __forceinline__ int32_t theta_index(int64_t Z, int32_t B, int32_t S)
+// min(max(v, lo), hi) for lo <= hi: one v_med3_i32 on the device.
+__host__ __device__ __forceinline__ int32_t med3_i32(int32_t v, int32_t lo, int32_t hi)
 {
-    const uint32_t zl = (uint32_t)Z;
-    const int32_t zh = (int32_t)(Z >> 32);
-    const uint64_t lo = (uint64_t)zl * (uint64_t)(uint32_t)B;
-    if (S > 32) {
-        const int32_t sh = S - 32;
-        int64_t hi = (int64_t)zh * (int64_t)B + (int64_t)(lo >> 32) + ((int64_t)1 << (sh - 1));
-        const int64_t lim = (int64_t)kThetaHalf << sh;
-        hi = hi < -lim ? -lim : hi;
-        hi = hi > lim ? lim : hi;
-        return (int32_t)(hi >> sh);
-    }
-    const uint64_t lo2 = lo + ((uint64_t)1 << (S - 1));
-    const int64_t hi = (int64_t)zh * (int64_t)B + (int64_t)(lo2 >> 32);
-    if (hi >= ((int64_t)1 << 20)) return kThetaHalf;
-    if (hi < -((int64_t)1 << 20)) return -kThetaHalf;
-    int64_t q = hi;
-    if (S < 32) q = hi * ((int64_t)1 << (32 - S)) + (int64_t)((uint32_t)lo2 >> S);
+#if defined(__HIP_DEVICE_COMPILE__)
+    int32_t r;
+    asm volatile("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "v"(lo), "v"(hi));
+    return r;
+#else
+    return v < lo ? lo : (v > hi ? hi : v);
+#endif
+}
+
+// Threshold index clamp(floor((Z*B + 2^(S-1)) / 2^S), -2304, 2304) for a
+// field carried as Z' = 2^u Z with S' = S + u >= 34 (the host picks u), without
+// a 128-bit product: Z*B = zh*B*2^32 + zl*B, so
+//   hi = floor((Z*B + 2^(S'-1)) / 2^32) = zh*B + (zl*B >> 32) + 2^(S'-33)
+// and the index is floor(hi / 2^(S'-32)).  The high word of hi is clamped first
+// so that the shifted value fits 32 bits while every out-of-range value still
+// lands beyond +-2304; then one 64-bit shift and one clamp finish it.
+__host__ __device__ __forceinline__ int32_t theta_index(int64_t Z, int32_t B, int32_t ish, int64_t irnd,
+                                               int32_t hclo, int32_t hchi)
+{
+    const uint64_t lo = (uint64_t)(uint32_t)Z * (uint64_t)(uint32_t)B;
+    const int64_t hi = (int64_t)(int32_t)(Z >> 32) * (int64_t)B + (int64_t)(lo >> 32) + irnd;
+    const int32_t H = med3_i32((int32_t)(hi >> 32), hclo, hchi);
+    const int64_t hc = (int64_t)(((uint64_t)(uint32_t)H << 32) | (uint64_t)(uint32_t)hi);
+    int32_t q = (int32_t)(hc >> ish);
     q = q < -kThetaHalf ? -kThetaHalf : q;
     q = q > kThetaHalf ? kThetaHalf : q;
-    return (int32_t)q;
+    return q;
 }
 
 // Four 0/1 bytes of a word -> four bits.

@@ -27,7 +27,7 @@ struct DevInstance {
     const int32_t *slack_off; // [m] first slack site of constraint k
     const int32_t *slack_q;   // [m] slack bits of constraint k
     // state
-    int64_t *kconst;          // [n_ext][2] K0_i, K1_i = per-site field constants at x_i = 0 / 1
+    int64_t *site;            // [n_pad][4] per-site record: K0, K1, c, meta (see below)
     int64_t *lam_acc;         // [m] lambda_n on a 2^-32 grid
     int32_t *lam_q;           // [m] lambda_n on a 2^-8 grid
     int32_t *round_k;         // [1] rounds completed
@@ -42,8 +42,12 @@ struct DevInstance {
     int32_t *rfeas;           // [R]
     // scalars
     int32_t n, m, n_ext, n_pad, words, owords, R, T, S, nq;
-    int32_t sg2;              // s_g^2 (quadratic kernel; < 2^31)
-    int32_t k2;               // 2 s_f Pq (< 2^31)
+    int32_t sg2;              // 2^u s_g^2 (quadratic kernel; < 2^31)
+    int32_t k2;               // 2^u 2 s_f Pq (< 2^31)
+    int32_t zsh;              // u: fields are carried as 2^u Z so that S + u >= 34
+    int32_t ish;              // S + u - 32 (>= 2)
+    int64_t irnd;             // 2^(S + u - 33): rounding term of the index, in units of 2^32
+    int32_t hclo, hchi;       // clamp of the index's high word before the final shift
     int64_t sfsg;             // s_f s_g
     int64_t lq_max;
     int64_t eta_num;
@@ -52,6 +56,12 @@ struct DevInstance {
     int32_t pad0;
 };
 
+// Per-site record (4 x int64), i < n_pad:
+//   K0, K1  2^u (256 s_g^2 h_i - s_f s_g a_i.lq - Sa_i (1 - 2 x_i)) for x_i = 0, 1
+//   c       2^u (256 s_g^2 W_{i,i-1} - 2 s_f Pq a_i.a_{i-1}): change of Z_i when
+//           site i-1 flips from 0 to 1 (0 where i-1 is not the preceding visit)
+//   meta    low word a_i (one-constraint kernel), high word -1 for a real
+//           site and 0 for padding
 enum Variant { kQuad = 0, kLinear = 1, kLinearWide = 2 };
 
 }  // namespace pbit

@@ -134,8 +134,8 @@ __global__ __launch_bounds__(256) void lambda_update(const DevInstance d, int mo
         int64_t al = 0;
         for (int c = 0; c < d.m; ++c) al += (int64_t)d.acol[(int64_t)i * d.m + c] * lq[c];
         const int64_t K0 = d.kbase[i] - d.sfsg * al;
-        d.kconst[2 * i] = K0;
-        d.kconst[2 * i + 1] = K0 + d.sa2[i];
+        d.site[4 * i] = K0 * ((int64_t)1 << d.zsh);
+        d.site[4 * i + 1] = (K0 + d.sa2[i]) * ((int64_t)1 << d.zsh);
     }
 }
 

@@ -20,6 +20,22 @@
 namespace pbit {
 
 template <int M, bool WIDE>
+__device__ __forceinline__ int64_t constraint_field(const int32_t *ac, const int32_t (&g)[M], int64_t k2)
+{
+    // 2 s_f Pq a_i.g (scaled), the only replica-dependent part of an item's field
+    if (WIDE) {
+        int64_t dd = 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) dd += (int64_t)ac[k] * (int64_t)g[k];
+        return dd * k2;
+    }
+    int32_t dd = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) dd += __mul24(ac[k], g[k]);
+    return (int64_t)dd * k2;
+}
+
+template <int M, bool WIDE>
 __global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -36,10 +52,12 @@ __global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
     const uint32_t kround = (uint32_t)d.round_k[0];
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int n = d.n;
-    const int64_t *__restrict__ kconst = d.kconst;
+    const int64_t *__restrict__ site = d.site;
     const int32_t *__restrict__ acol = d.acol;
     const int32_t *__restrict__ Btab = d.Btab;
     const int64_t k2 = d.k2;
+    const int32_t ish = d.ish, hclo = d.hclo, hchi = d.hchi;
+    const int64_t irnd = d.irnd;
 
     int32_t g[M];
     uint32_t sk[M];
@@ -52,70 +70,91 @@ __global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
     for (int t = 0; t < d.T; ++t) {
         const int32_t Bt = Btab[t];
         const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
-        // original items
+        // original items, 32 per word of state
         for (int blk = 0; blk < d.owords; ++blk) {
             uint32_t xw = xl[blk * kWave + lane];
+            const int64_t *rec = site + 4 * (blk * 32);
+            const int32_t *ac0 = acol + (int64_t)(blk * 32) * M;
             uint32_t rnd[4] = {0u, 0u, 0u, 0u};
+            uint32_t thA, thB, pend = 0u;
+            {
+                const int64_t Z = ((xw & 1u) ? rec[1] : rec[0]) - constraint_field<M, WIDE>(ac0, g, k2);
+                thA = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
+                thB = thA;
+            }
 #pragma unroll
             for (int s = 0; s < 32; ++s) {
-                const int i = blk * 32 + s;
-                if (i < n) {
-                    if ((s & 3) == 0)
-                        philox_block(cbase + (uint32_t)(i >> 2), kround, m2, d.inst_id, d.seed_lo,
-                                     d.seed_hi, rnd);
-                    const uint32_t u24 = rnd[s & 3] >> 8;
-                    const uint32_t xo = (xw >> s) & 1u;
-                    const int64_t K0 = kconst[2 * i];
-                    const int64_t K1 = kconst[2 * i + 1];
-                    const int32_t *ac = acol + (int64_t)i * M;
-                    int64_t Z;
-                    if (WIDE) {
-                        int64_t dd = 0;
-#pragma unroll
-                        for (int k = 0; k < M; ++k) dd += (int64_t)ac[k] * (int64_t)g[k];
-                        Z = (xo ? K1 : K0) - dd * k2;
-                    } else {
-                        int32_t dd = 0;
-#pragma unroll
-                        for (int k = 0; k < M; ++k) dd += __mul24(ac[k], g[k]);
-                        Z = (xo ? K1 : K0) - (int64_t)dd * k2;
-                    }
-                    const int32_t idx = theta_index(Z, Bt, d.S);
-                    const uint32_t xn = u24 < (uint32_t)th[idx + kThetaHalf] ? 1u : 0u;
-                    const int32_t delta = (int32_t)xn - (int32_t)xo;
-#pragma unroll
-                    for (int k = 0; k < M; ++k) g[k] += delta * ac[k];
-                    xw = (xw & ~(1u << s)) | (xn << s);
+                const uint32_t xo = (xw >> s) & 1u;
+                uint32_t nA = 0u, nB = 0u;
+                if (s < 31) {
+                    const int64_t *nx = rec + 4 * (s + 1);
+                    const uint32_t xo1 = (xw >> (s + 1)) & 1u;
+                    const int64_t Z0 = (xo1 ? nx[1] : nx[0]) -
+                                       constraint_field<M, WIDE>(ac0 + (s + 1) * M, g, k2);
+                    const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
+                    nA = (uint32_t)th[theta_index(Z0, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
+                    nB = (uint32_t)th[theta_index(Z1, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
                 }
+                if ((s & 3) == 0)
+                    philox_block(cbase + (uint32_t)((blk * 32 + s) >> 2), kround, m2, d.inst_id,
+                                 d.seed_lo, d.seed_hi, rnd);
+                const uint32_t u24 = rnd[s & 3] >> 8;
+                const uint32_t thr = (pend ? thB : thA) & (uint32_t)(rec[4 * s + 3] >> 32);
+                const uint32_t xn = u24 < thr ? 1u : 0u;
+                const int32_t delta = (int32_t)xn - (int32_t)xo;
+                pend = xn ^ xo;
+                const int32_t *ac = ac0 + s * M;
+#pragma unroll
+                for (int k = 0; k < M; ++k) g[k] += delta * ac[k];
+                xw = (xw & ~(1u << s)) | (xn << s);
+                thA = nA;
+                thB = nB;
             }
             xl[blk * kWave + lane] = xw;
         }
-        // slack bits, constraint by constraint
+        // slack bits, constraint by constraint: a slack bit q of constraint k
+        // has a = 2^q e_k, so its field only needs g_k
         uint32_t rnd[4] = {0u, 0u, 0u, 0u};
         int grp = -1;
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int off = d.slack_off[k];
             const int Qk = d.slack_q[k];
-            for (int q = 0; q < Qk; ++q) {
-                const int i = off + q;
-                if ((i >> 2) != grp) {
-                    grp = i >> 2;
-                    philox_block(cbase + (uint32_t)grp, kround, m2, d.inst_id, d.seed_lo, d.seed_hi,
-                                 rnd);
+            if (Qk > 0) {
+                uint32_t thA, thB, pend = 0u;
+                {
+                    const int64_t *rec = site + 4 * off;
+                    const int64_t Z = ((sk[k] & 1u) ? rec[1] : rec[0]) - (int64_t)g[k] * k2;
+                    thA = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
+                    thB = thA;
                 }
-                const int sel = i & 3;
-                const uint32_t word = sel == 0 ? rnd[0] : sel == 1 ? rnd[1] : sel == 2 ? rnd[2] : rnd[3];
-                const uint32_t u24 = word >> 8;
-                const uint32_t xo = (sk[k] >> q) & 1u;
-                const int64_t K0 = kconst[2 * i];
-                const int64_t K1 = kconst[2 * i + 1];
-                const int64_t Z = (xo ? K1 : K0) - ((int64_t)g[k] * k2) * ((int64_t)1 << q);
-                const int32_t idx = theta_index(Z, Bt, d.S);
-                const uint32_t xn = u24 < (uint32_t)th[idx + kThetaHalf] ? 1u : 0u;
-                const int32_t delta = (int32_t)xn - (int32_t)xo;
-                g[k] += delta * (1 << q);
-                sk[k] = (sk[k] & ~(1u << q)) | (xn << q);
+                for (int q = 0; q < Qk; ++q) {
+                    const int i = off + q;
+                    const uint32_t xo = (sk[k] >> q) & 1u;
+                    // both thresholds of bit q+1 (the record past the last bit is padding)
+                    const int64_t *nx = site + 4 * (i + 1);
+                    const uint32_t xo1 = (sk[k] >> (q + 1)) & 1u;
+                    const int64_t Z0 = (xo1 ? nx[1] : nx[0]) - ((int64_t)g[k] * k2) * ((int64_t)2 << q);
+                    const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
+                    const uint32_t nA = (uint32_t)th[theta_index(Z0, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
+                    const uint32_t nB = (uint32_t)th[theta_index(Z1, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
+                    if ((i >> 2) != grp) {
+                        grp = i >> 2;
+                        philox_block(cbase + (uint32_t)grp, kround, m2, d.inst_id, d.seed_lo,
+                                     d.seed_hi, rnd);
+                    }
+                    const int sel = i & 3;
+                    const uint32_t word = sel == 0 ? rnd[0] : sel == 1 ? rnd[1] : sel == 2 ? rnd[2] : rnd[3];
+                    const uint32_t u24 = word >> 8;
+                    const uint32_t thr = pend ? thB : thA;
+                    const uint32_t xn = u24 < thr ? 1u : 0u;
+                    const int32_t delta = (int32_t)xn - (int32_t)xo;
+                    pend = xn ^ xo;
+                    g[k] += delta * (1 << q);
+                    sk[k] = (sk[k] & ~(1u << q)) | (xn << q);
+                    thA = nA;
+                    thB = nB;
+                }
             }
         }
     }

@@ -1,0 +1,60 @@
+// Host check of the sampling kernels' threshold-index arithmetic: compares
+// theta_index (the same inline function the GPU kernels call) with the plain
+// definition clamp(floor((Z*B + 2^(S-1)) / 2^S), -2304, 2304) evaluated in
+// 128-bit integers, over random and boundary inputs.  Prints the number of
+// mismatches and exits nonzero if there is any.
+#include <cstdio>
+#include <cstdint>
+#include <random>
+
+#include "../paper_2501_04971_amd/csrc/device_common.h"
+
+typedef __int128 i128;
+
+static int32_t reference(int64_t Z, int32_t B, int S)
+{
+    i128 v = (i128)Z * B + ((i128)1 << (S - 1));
+    i128 d = (i128)1 << S;
+    i128 q = v / d;
+    if (v % d != 0 && v < 0) q -= 1;
+    if (q > 2304) q = 2304;
+    if (q < -2304) q = -2304;
+    return (int32_t)q;
+}
+
+int main()
+{
+    std::mt19937_64 rng(12345);
+    long bad = 0, total = 0;
+    for (int S = 34; S <= 94; ++S) {
+        const int ish = S - 32;
+        const int64_t irnd = (int64_t)1 << (S - 33);
+        const int32_t hclo = ish <= 31 ? -(int32_t)(1u << (ish - 1)) : INT32_MIN;
+        const int32_t hchi = ish <= 31 ? (int32_t)((1u << (ish - 1)) - 1u) : INT32_MAX;
+        for (int it = 0; it < 20000; ++it) {
+            const int32_t B = it == 0 ? 0 : it == 1 ? INT32_MAX : (int32_t)(rng() >> 33);
+            int64_t Z;
+            const int mode = it % 4;
+            if (mode == 0) {
+                Z = (int64_t)(rng() >> 2) * ((rng() & 1) ? 1 : -1);            // |Z| < 2^62
+            } else if (mode == 1) {
+                Z = (int64_t)(rng() >> (2 + rng() % 60)) * ((rng() & 1) ? 1 : -1);
+            } else {
+                // near the saturation boundary and the rounding midpoints
+                if (B == 0) continue;
+                const long double target = (mode == 2 ? 2304.5L : (long double)((int)(rng() % 4609) - 2304) + 0.5L) *
+                                           ((rng() & 1) ? 1 : -1);
+                const long double z = target * powl(2.0L, S) / (long double)B;
+                if (fabsl(z) > 4.0e18L) continue;
+                Z = (int64_t)z + (int64_t)(rng() % 5) - 2;
+            }
+            ++total;
+            if (pbit::theta_index(Z, B, ish, irnd, hclo, hchi) != reference(Z, B, S)) {
+                if (bad < 10) std::printf("mismatch S=%d Z=%lld B=%d\n", S, (long long)Z, B);
+                ++bad;
+            }
+        }
+    }
+    std::printf("checked %ld cases, %ld mismatches\n", total, bad);
+    return bad ? 1 : 0;
+}
