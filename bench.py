@@ -26,8 +26,9 @@ import time
 # (8), the threshold compare (2) and the state/residual update (2 + 2M).
 ALU_OPS_RNG = 20
 ALU_OPS_FIXED = 12
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz 32-bit integer lane-ops per second.
-ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz 32-bit lane-ops per second (the fp32
+# vector peak of 157.3 TFLOP/s counts an FMA as two operations).
+ALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 
 
 def alu_ops_per_update(m: int) -> int:
