@@ -26,8 +26,7 @@
 #include "pbit_types.h"
 
 namespace pbit {
-hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, bool lookahead,
-                             hipStream_t stream);
+hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
 hipError_t launch_sweep_linear_a(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
 hipError_t launch_sweep_linear_b(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
 hipError_t launch_sweep_linear_c(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
@@ -390,10 +389,13 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     P.hprof.resize(n);
     for (int i = 0; i < n; ++i) P.hprof[i] = (int32_t)h[i];
     if (P.variant == kQuad) {
+        // slabs of 32 rows (row stride n_pad + 16 bytes), slab stride 1 KB x (nb + 1)
         const int ls = P.n_pad + 16;
-        P.J.assign((size_t)P.n_pad * ls, 0);
+        const size_t slab = (size_t)1024 * (P.nb + 1);
+        P.J.assign((size_t)P.nb * slab, 0);
         for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) P.J[(size_t)i * ls + j] = (int8_t)W[(size_t)i * n + j];
+            for (int j = 0; j < n; ++j)
+                P.J[(size_t)(i / 32) * slab + (size_t)(i % 32) * ls + j] = (int8_t)W[(size_t)i * n + j];
     }
     if (!make_theta(P.theta)) return fail(PBIT_ERANGE, "threshold table rounding undecidable");
 
@@ -481,7 +483,6 @@ struct pbit_instance {
     std::vector<unsigned char> upload;
     int device = 0;
     int wpb = 1;
-    bool lookahead = false;
     bool broken = false;
 };
 
@@ -630,7 +631,6 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
     d.seed_hi = (uint32_t)(P.seed >> 32);
     d.inst_id = P.inst;
     inst->wpb = waves_per_block(P);
-    if (const char *e = std::getenv("PBIT_LOOKAHEAD")) inst->lookahead = std::atoi(e) != 0;
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     e = hipMemcpyAsync(dev_ws, inst->upload.data(), L.upload_end, hipMemcpyHostToDevice, s);
@@ -654,7 +654,7 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
     hipError_t e;
     switch (inst->plan.variant) {
         case kQuad:
-            e = launch_sweep_quad(d, inst->plan.nb, inst->wpb, inst->lookahead, s);
+            e = launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
             break;
         default: {
             const bool wide = inst->plan.variant == kLinearWide;

@@ -16,7 +16,7 @@ constexpr int kWave = 64;
 // Everything a kernel needs about one instance; passed by value.
 struct DevInstance {
     // constants written once at create
-    const int8_t *J;          // quadratic: [n_pad][n_pad + 16] pair profits, zero diagonal
+    const int8_t *J;          // quadratic: slabs of 32 rows x (n_pad + 16) bytes, slab stride 1 KB x (nb + 1)
     const int32_t *theta;     // [kThetaLen]
     const int32_t *Btab;      // [T] beta grid
     const int32_t *acol;      // [n_ext][m] extended constraint coefficients, site-major
@@ -35,6 +35,7 @@ struct DevInstance {
     int64_t *best;            // [4] profit, round, replica, valid
     uint32_t *best_x;         // [words]
     int32_t *feas_count;      // [1] feasible replicas of the last round
+    int32_t *rounds_left;     // [1] multiplier steps still to run (batch members), or null
     // per-replica outputs of the last round
     uint32_t *rx;             // [R][words]
     int32_t *rg;              // [R][m]

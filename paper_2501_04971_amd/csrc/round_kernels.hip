@@ -19,7 +19,7 @@ __device__ __forceinline__ bool better(int64_t p, int32_t r, int64_t q, int32_t 
     return p > q || (p == q && r < s);
 }
 
-__global__ __launch_bounds__(kReduceThreads) void round_reduce(const DevInstance d)
+__device__ __forceinline__ void round_reduce_body(const DevInstance &d)
 {
     __shared__ int64_t sp[kReduceThreads];
     __shared__ int32_t sr[kReduceThreads];
@@ -112,7 +112,7 @@ struct LambdaSet {
 };
 
 // mode 0: refresh constants only; 1: multiplier step from d.G; 2: set lambda_q from `set`.
-__global__ __launch_bounds__(256) void lambda_update(const DevInstance d, int mode, LambdaSet set)
+__device__ __forceinline__ void lambda_update_body(const DevInstance &d, int mode, const LambdaSet &set)
 {
     __shared__ int32_t lq[kMaxM];
     const int tid = threadIdx.x;
@@ -137,6 +137,61 @@ __global__ __launch_bounds__(256) void lambda_update(const DevInstance d, int mo
         d.site[4 * i] = K0 * ((int64_t)1 << d.zsh);
         d.site[4 * i + 1] = (K0 + d.sa2[i]) * ((int64_t)1 << d.zsh);
     }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void round_reduce(const DevInstance d)
+{
+    round_reduce_body(d);
+}
+
+__global__ __launch_bounds__(256) void lambda_update(const DevInstance d, int mode, LambdaSet set)
+{
+    lambda_update_body(d, mode, set);
+}
+
+// Batched forms: workgroup b serves instance b.  Members whose round budget is
+// spent are skipped; the multiplier step consumes one unit of the budget.
+__global__ __launch_bounds__(kReduceThreads) void round_reduce_batch(const DevInstance *insts)
+{
+    const DevInstance d = insts[blockIdx.x];
+    if (d.rounds_left && d.rounds_left[0] <= 0) return;
+    round_reduce_body(d);
+}
+
+__global__ __launch_bounds__(256) void lambda_update_batch(const DevInstance *insts, int mode)
+{
+    const DevInstance d = insts[blockIdx.x];
+    if (mode == 1 && d.rounds_left && d.rounds_left[0] <= 0) return;
+    LambdaSet none{};
+    lambda_update_body(d, mode, none);
+    __syncthreads();
+    if (mode == 1 && d.rounds_left && threadIdx.x == 0) d.rounds_left[0] -= 1;
+}
+
+__global__ void reset_counter(int *counter)
+{
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+hipError_t launch_round_reduce_batch(const DevInstance *insts, int count, hipStream_t stream)
+{
+    void *args[] = {&insts};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&round_reduce_batch), dim3(count),
+                           dim3(kReduceThreads), args, 0, stream);
+}
+
+hipError_t launch_lambda_update_batch(const DevInstance *insts, int count, int mode, hipStream_t stream)
+{
+    void *args[] = {&insts, &mode};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&lambda_update_batch), dim3(count), dim3(256),
+                           args, 0, stream);
+}
+
+hipError_t launch_reset_counter(int *counter, hipStream_t stream)
+{
+    void *args[] = {&counter};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&reset_counter), dim3(1), dim3(64), args, 0,
+                           stream);
 }
 
 hipError_t launch_round_reduce(const DevInstance &d, hipStream_t stream)

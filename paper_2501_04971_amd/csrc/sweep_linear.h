@@ -35,10 +35,18 @@ __device__ __forceinline__ int64_t constraint_field(const int32_t *ac, const int
     return (int64_t)dd * k2;
 }
 
-template <int M, bool WIDE>
-__global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
+// LDS bytes of linear_run for a workgroup of wpb waves and `words` state words.
+inline size_t linear_lds_bytes(int wpb, int words)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
+    return (size_t)kThetaBytes + (size_t)wpb * words * kWave * 4;
+}
+
+// One annealing run (T sweeps) of the replicas rbase + [0, blockDim.x) of
+// instance d, then the scoring of the final states.  smem must hold
+// linear_lds_bytes(blockDim.x / 64, d.words) bytes.
+template <int M, bool WIDE>
+__device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsigned char *smem)
+{
     int32_t *th = reinterpret_cast<int32_t *>(smem);
     const int lane = threadIdx.x & 63;
     const int wave_in_block = threadIdx.x >> 6;
@@ -48,7 +56,7 @@ __global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
     for (int w = 0; w < d.words; ++w) xl[w * kWave + lane] = 0u;
     __syncthreads();
 
-    const int r = (blockIdx.x * (blockDim.x >> 6) + wave_in_block) * kWave + lane;
+    const int r = rbase + threadIdx.x;
     const uint32_t kround = (uint32_t)d.round_k[0];
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int n = d.n;
@@ -191,15 +199,18 @@ __global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
     }
 }
 
-}  // namespace pbit
-
-namespace pbit {
+template <int M, bool WIDE>
+__global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    linear_run<M, WIDE>(d, blockIdx.x * blockDim.x, smem);
+}
 
 inline hipError_t launch_linear_kernel(const void *kern, const DevInstance &d, int waves_per_block,
                                        hipStream_t stream)
 {
     const int wpb = waves_per_block < 1 ? 1 : waves_per_block;
-    const size_t lds = (size_t)kThetaBytes + (size_t)wpb * d.words * kWave * 4;
+    const size_t lds = linear_lds_bytes(wpb, d.words);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int waves = (d.R + kWave - 1) / kWave;

@@ -1,298 +1,28 @@
-// Annealing run for instances with pair profits (quadratic knapsack, one
-// constraint): the p-bit machine of Sec. III-B, one replica per lane.
-//
-// Field of site i for replica r (Eq. Ii_eq in the 0/1 form, all integers):
-//   Z_i = 256 s_g^2 F_i + K_{x_i,i} - 2 s_f Pq a_i g
-// with F_i = sum_j W_ij x_j, g = a.x - b the residual, and K_{0,i}, K_{1,i} the
-// per-site constants of the current lambda (h_i, the penalty's self term and
-// the Lagrange term folded in).  The update of Eq. mi_eq is
-//   x_i <- [u24 < Theta[round(beta_t Z_i / (2 s_f s_g^2))]].
-//
-// Layout: the int8 profit block W (n_pad x n_pad, rows padded by 16 bytes),
-// the per-site records and the threshold table sit in LDS.  Each lane keeps its replica's state as
-// n_pad bytes in VGPRs.  Sites are visited in blocks of 32: at the start of a
-// block the 32 fields of the block are recomputed for all 64 replicas of the
-// wave with int8 MFMA (W[blk, :] . x); inside the block the earlier flips are
-// added with packed int8 dot products (W[i, blk] . dx).  The penalty is never
-// expanded into couplings: the constraint enters through the residual g.
-//
-// Visit pipeline: a flip of site s moves the field of site s+1 by the known
-// per-site constant c_{s+1} (Z_{s+1} = P + delta_s c_{s+1}), so while site s is
-// being decided both thresholds of site s+1 (s flips / s stays) are computed;
-// the dependent chain per visit is then one select, one compare and one xor.
-//
-// Register layout of the state: chunk c (sites 32c..32c+31) is 8 dwords per
-// lane.  Outside its own block a chunk is stored in the MFMA B-operand layout
-// (lanes 0..31 hold sites 0..15 of replicas 0..31 / 32..63, lanes 32..63 sites
-// 16..31), which one permlane32 swap per dword pair converts to and from the
-// owner layout (lane r holds all 32 bytes of replica r).  The chunk of the
-// current block is kept at register position 0: positions rotate by one chunk
-// per block, so all indexing is static.
-#include <utility>
-
-#include "device_common.h"
+// Single-instance launches of the quadratic annealing kernel (see sweep_quad.h).
+#include "sweep_quad.h"
 
 namespace pbit {
 
-template <int NB>
-__device__ __forceinline__ void block_fields(const int8_t *arow, int blk, const uint32_t (&x)[NB][8],
-                                             int32_t (&F)[32])
+template <int NB, int WPB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sweep_quad(const DevInstance d)
 {
-    constexpr int LS = NB * 32 + 16;
-    v16i acc0 = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    v16i acc1 = acc0;
-    const int8_t *ablk = arow + blk * 32 * LS;
-#pragma unroll
-    for (int p = 0; p < NB; ++p) {
-        int c = p + blk;
-        c = c >= NB ? c - NB : c;
-        const v4i A = *reinterpret_cast<const v4i *>(ablk + c * 32);
-        const v4i B0 = {(int)x[p][0], (int)x[p][1], (int)x[p][2], (int)x[p][3]};
-        const v4i B1 = {(int)x[p][4], (int)x[p][5], (int)x[p][6], (int)x[p][7]};
-        acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B1, acc1, 0, 0, 0);
-    }
-    // accumulator row 8(v/4) + 4(lane/32) + v%4, column lane%32 -> owner layout
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        uint32_t lo = (uint32_t)acc0[v], hi = (uint32_t)acc1[v];
-        swap_halves(lo, hi);
-        F[8 * (v >> 2) + (v & 3)] = (int32_t)lo;
-        F[8 * (v >> 2) + 4 + (v & 3)] = (int32_t)hi;
-    }
-}
-
-template <int NB>
-__device__ __forceinline__ void rotate_chunks(uint32_t (&x)[NB][8])
-{
-    uint32_t tmp[8];
-#pragma unroll
-    for (int w = 0; w < 8; ++w) tmp[w] = x[0][w];
-#pragma unroll
-    for (int p = 0; p + 1 < NB; ++p)
-#pragma unroll
-        for (int w = 0; w < 8; ++w) x[p][w] = x[p + 1][w];
-#pragma unroll
-    for (int w = 0; w < 8; ++w) x[NB - 1][w] = tmp[w];
-}
-
-// Registers of one block of 32 visits, shared by the unrolled steps.
-struct BlockVisit {
-    const int64_t *rec;      // per-site records of the block
-    const int8_t *wblk;      // LDS: W[blk*32 .., blk*32 ..]
-    const int32_t *th;       // LDS threshold table
-    int32_t F[32];           // block fields at the block start
-    uint32_t dx[8];          // packed int8 flips of this block
-    uint32_t rnd[4];
-    uint32_t thA, thB, pend;
-    int32_t g;
-    int32_t Bt, ish, hclo, hchi;
-    int64_t irnd, sg2, k2;
-    uint32_t cbase, kround, inst, seed_lo, seed_hi;
-    uint64_t m2;
-    int blk;
-};
-
-// One visit of site s of the block: compute both thresholds of site s+1 from
-// the state before s moves, then decide s (Eq. mi_eq) and apply its flip.
-template <int s, int LS>
-__device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8])
-{
-    const uint32_t xo = (xc[s >> 2] >> (8 * (s & 3))) & 1u;
-    uint32_t nA = 0u, nB = 0u;
-    if constexpr (s < 31) {
-        const int64_t *nx = v.rec + 4 * (s + 1);
-        int32_t f = v.F[s + 1];
-        const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + (s + 1) * LS);
-#pragma unroll
-        for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
-        const uint32_t xo1 = (xc[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 1u;
-        const int64_t Z0 = (xo1 ? nx[1] : nx[0]) + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)nx[3], v.g) * v.k2;
-        const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
-        nA = (uint32_t)v.th[theta_index(Z0, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
-        nB = (uint32_t)v.th[theta_index(Z1, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
-    }
-    if constexpr ((s & 3) == 0)
-        philox_block(v.cbase + (uint32_t)((v.blk * 32 + s) >> 2), v.kround, v.m2, v.inst, v.seed_lo,
-                     v.seed_hi, v.rnd);
-    const uint32_t u24 = v.rnd[s & 3] >> 8;
-    const int64_t meta = v.rec[4 * s + 3];
-    const uint32_t thr = (v.pend ? v.thB : v.thA) & (uint32_t)(meta >> 32);
-    const uint32_t xn = u24 < thr ? 1u : 0u;
-    const int32_t delta = (int32_t)xn - (int32_t)xo;
-    v.pend = xn ^ xo;
-    xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
-    v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
-    v.g += __mul24(delta, (int32_t)meta);
-    v.thA = nA;
-    v.thB = nB;
-}
-
-// One visit of site s without lookahead: its threshold is computed from the
-// current state right before the decision.
-template <int s, int LS>
-__device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[8])
-{
-    const uint32_t xo = (xc[s >> 2] >> (8 * (s & 3))) & 1u;
-    const int64_t *cur = v.rec + 4 * s;
-    int32_t f = v.F[s];
-    const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + s * LS);
-#pragma unroll
-    for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
-    const int64_t meta = cur[3];
-    const int64_t Z = (xo ? cur[1] : cur[0]) + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
-    const uint32_t thr = (uint32_t)v.th[theta_index(Z, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf] &
-                         (uint32_t)(meta >> 32);
-    if constexpr ((s & 3) == 0)
-        philox_block(v.cbase + (uint32_t)((v.blk * 32 + s) >> 2), v.kround, v.m2, v.inst, v.seed_lo,
-                     v.seed_hi, v.rnd);
-    const uint32_t u24 = v.rnd[s & 3] >> 8;
-    const uint32_t xn = u24 < thr ? 1u : 0u;
-    const int32_t delta = (int32_t)xn - (int32_t)xo;
-    xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
-    v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
-    v.g += __mul24(delta, (int32_t)meta);
-}
-
-template <int LS, bool LA, int... S>
-__device__ __forceinline__ void visit_block(BlockVisit &v, uint32_t (&xc)[8], std::integer_sequence<int, S...>)
-{
-    if constexpr (LA)
-        (visit_site<S, LS>(v, xc), ...);
-    else
-        (visit_site_direct<S, LS>(v, xc), ...);
-}
-
-template <int NB, bool LA>
-__global__ __launch_bounds__(256) void sweep_quad(const DevInstance d)
-{
-    constexpr int NP = NB * 32;        // padded spin count
-    constexpr int LS = NP + 16;        // LDS row stride of W (bytes)
     extern __shared__ __align__(16) unsigned char smem[];
-    int32_t *th = reinterpret_cast<int32_t *>(smem);
-    int64_t *site = reinterpret_cast<int64_t *>(smem + kThetaBytes);
-    int8_t *Wl = reinterpret_cast<int8_t *>(smem + kThetaBytes + NP * 32);
-
-    for (int e = threadIdx.x; e < kThetaLen; e += blockDim.x) th[e] = d.theta[e];
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(d.site);
-        uint4 *dst = reinterpret_cast<uint4 *>(site);
-        for (int e = threadIdx.x; e < NP * 2; e += blockDim.x) dst[e] = src[e];
-    }
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(d.J);
-        uint4 *dst = reinterpret_cast<uint4 *>(Wl);
-        for (int e = threadIdx.x; e < NP * LS / 16; e += blockDim.x) dst[e] = src[e];
-    }
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63;
-    const int r = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * kWave + lane;
-    const uint32_t kround = (uint32_t)d.round_k[0];
-    const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
-    const int32_t *__restrict__ Btab = d.Btab;
-
-    uint32_t x[NB][8];
-#pragma unroll
-    for (int p = 0; p < NB; ++p)
-#pragma unroll
-        for (int w = 0; w < 8; ++w) x[p][w] = 0u;
-    // A operand of the block field: row blk*32 + (lane & 31), bytes 16*(lane>>5)..+15 of chunk c
-    const int8_t *arow = Wl + (lane & 31) * LS + (lane >> 5) * 16;
-
-    BlockVisit v;
-    v.th = th;
-    v.g = -(int32_t)d.b[0];
-    v.ish = d.ish;
-    v.hclo = d.hclo;
-    v.hchi = d.hchi;
-    v.irnd = d.irnd;
-    v.sg2 = d.sg2;
-    v.k2 = d.k2;
-    v.kround = kround;
-    v.inst = d.inst_id;
-    v.seed_lo = d.seed_lo;
-    v.seed_hi = d.seed_hi;
-    v.m2 = m2;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) v.rnd[w] = 0u;
-
-    for (int t = 0; t < d.T; ++t) {
-        v.Bt = Btab[t];
-        v.cbase = (uint32_t)t * (uint32_t)d.nq;
-        for (int blk = 0; blk < NB; ++blk) {
-            block_fields<NB>(arow, blk, x, v.F);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
-
-            v.rec = site + 4 * (blk * 32);
-            v.wblk = Wl + blk * 32 * LS + blk * 32;
-            v.blk = blk;
-#pragma unroll
-            for (int w = 0; w < 8; ++w) v.dx[w] = 0u;
-            // thresholds of site 0 (nothing pending at a block start)
-            if constexpr (LA) {
-                const uint32_t xo0 = x[0][0] & 1u;
-                const int64_t Z = (xo0 ? v.rec[1] : v.rec[0]) + (int64_t)(v.F[0] * 256) * v.sg2 -
-                                  (int64_t)__mul24((int32_t)v.rec[3], v.g) * v.k2;
-                v.thA = (uint32_t)th[theta_index(Z, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
-                v.thB = v.thA;
-                v.pend = 0u;
-            }
-            visit_block<LS, LA>(v, x[0], std::make_integer_sequence<int, 32>{});
-#pragma unroll
-            for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
-            rotate_chunks<NB>(x);
-        }
-    }
-
-    // Score the final state: profit = (sum_{i<n} x_i (2 h_i + F_i)) / 2 with
-    // F = W x, slack value s = sum_q 2^q x_{n+q}; feasible iff g <= s.
-    const int n = d.n, n_ext = d.n_ext;
-    const bool live = r < d.R;
-    int64_t pacc = 0;
-    int32_t sval = 0;
-    for (int blk = 0; blk < NB; ++blk) {
-        int32_t F[32];
-        block_fields<NB>(arow, blk, x, F);
-#pragma unroll
-        for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
-        uint32_t bits = 0;
-#pragma unroll
-        for (int w = 0; w < 8; ++w) bits |= bytes_to_nibble(x[0][w]) << (4 * w);
-        if (live && blk < d.words) d.rx[(int64_t)r * d.words + blk] = bits;
-#pragma unroll
-        for (int s = 0; s < 32; ++s) {
-            const int i = blk * 32 + s;
-            const int32_t xb = (int32_t)((bits >> s) & 1u);
-            if (i < n) {
-                const int32_t v2 = 2 * d.hprof[i] + F[s];
-                pacc += (int64_t)(v2 & -xb);
-            } else if (i < n_ext) {
-                sval += xb << (i - n);
-            }
-        }
-#pragma unroll
-        for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
-        rotate_chunks<NB>(x);
-    }
-    if (live) {
-        d.rprofit[r] = pacc / 2;
-        d.rfeas[r] = v.g <= sval ? 1 : 0;
-        d.rg[r] = v.g;
-    }
+    quad_run<NB, WPB, false>(d, blockIdx.x * WPB * kWave, smem);
 }
 
 #define PBIT_QUAD_CASE(nb)                                                                  \
     case nb:                                                                                \
-        kern = lookahead ? reinterpret_cast<const void *>(&sweep_quad<nb, true>)            \
-                         : reinterpret_cast<const void *>(&sweep_quad<nb, false>);          \
+        kern = wpb == 1 ? reinterpret_cast<const void *>(&sweep_quad<nb, 1>)                \
+                        : reinterpret_cast<const void *>(&sweep_quad<nb, 4>);               \
+        lds = quad_lds_bytes<nb>();                                                         \
         break;
 
-hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, bool lookahead,
-                             hipStream_t stream)
+// waves_per_block: 1 or 4 (other values round to 4)
+hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream)
 {
     const void *kern = nullptr;
+    size_t lds = 0;
+    const int wpb = waves_per_block == 1 ? 1 : 4;
     switch (nb) {
         PBIT_QUAD_CASE(1) PBIT_QUAD_CASE(2) PBIT_QUAD_CASE(3) PBIT_QUAD_CASE(4) PBIT_QUAD_CASE(5)
         PBIT_QUAD_CASE(6) PBIT_QUAD_CASE(7) PBIT_QUAD_CASE(8) PBIT_QUAD_CASE(9) PBIT_QUAD_CASE(10)
@@ -300,12 +30,9 @@ hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, 
         default:
             return hipErrorInvalidValue;
     }
-    const int np = nb * 32;
-    const size_t lds = (size_t)kThetaBytes + (size_t)np * 32 + (size_t)np * (np + 16);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int waves = (d.R + kWave - 1) / kWave;
-    const int wpb = waves_per_block < 1 ? 1 : waves_per_block;
     const int blocks = (waves + wpb - 1) / wpb;
     void *args[] = {const_cast<DevInstance *>(&d)};
     return hipLaunchKernel(kern, dim3(blocks), dim3(wpb * kWave), args, lds, stream);

@@ -88,9 +88,11 @@ def test_qkp_table1_settings_multiplier_moves(need_gpu):
 
 
 @pytest.mark.parametrize("n,d,R", [(5, Fraction(1, 2), 64), (20, Fraction(1), 100),
-                                   (97, Fraction(3, 4), 130), (330, Fraction(1, 4), 64)])
+                                   (80, Fraction(1, 2), 64), (97, Fraction(3, 4), 130),
+                                   (200, Fraction(1, 4), 192), (330, Fraction(1, 4), 64)])
 def test_qkp_ragged_shapes(need_gpu, n, d, R):
-    """Partial site blocks, phantom lanes (R not a multiple of 64), one to eleven blocks."""
+    """Partial site blocks, phantom lanes (R not a multiple of 64), one to eleven blocks
+    (odd and even block counts: the slab buffers alternate across the sweep wrap)."""
     prob = G.qkp(n, d, G.rng_for(920, n))
     par = G.Params(replicas=R, sweeps=40, beta=Fraction(4), eta=Fraction(2))
     run_parity(prob, par, 3, label=f"QKP ragged n={n}")
