@@ -176,6 +176,76 @@ pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes,
  * synchronise: the caller must not free the workspace while work is queued. */
 pbit_status pbit_destroy_instance(pbit_instance *inst);
 
+/* Describes a created instance (as pbit_plan does for its inputs). */
+pbit_status pbit_instance_info(const pbit_instance *inst, pbit_plan_info *out);
+
+/* Launch layout of the single-instance sampling kernel: waves_per_block is the
+ * number of 64-replica waves per workgroup (quadratic kernel 1 or 4, linear
+ * kernel 1..4; 0 = the default for the replica count).  lds_resident selects,
+ * for the linear kernel, whether the per-site field constants and coefficient
+ * rows are staged in LDS (1), read from global memory (0), or staged whenever
+ * they fit (-1, the default); ignored by the quadratic kernel.  Every layout
+ * gives bit-identical results; only the speed differs.  Host only, takes
+ * effect at the next pbit_sample_round.  PBIT_ERANGE if lds_resident = 1 does
+ * not fit the 160 KB of LDS at this tiling. */
+pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_t lds_resident);
+
+/* ---- Batched execution --------------------------------------------------
+ * A batch runs many independent instances, of either kind and of uneven
+ * sizes, each with its own parameters (Tables 2-5 solve every instance on its
+ * own, so batching changes no result).  One round of the batch is one
+ * persistent kernel launch: workgroups of 256 replicas take work items
+ * (instance, replica tile) from a queue sorted by decreasing estimated cost
+ * through an atomic counter; then the round epilogue and the multiplier step
+ * run for every instance that still has rounds in its budget.  Every member
+ * produces exactly what a single instance created from the same problem and
+ * parameters produces.  Multi-knapsack members whose constraint count has no
+ * compiled batch body (1-6, 8, 10, 16, 30 and 32 do) are padded with empty
+ * constraints (zero weights, zero capacity), which changes no sample; their
+ * lambda and residual vectors then carry the extra zero entries. */
+typedef struct pbit_batch pbit_batch; /* opaque */
+
+/* Workspace bytes for a batch of count instances; 0 if any pair is invalid. */
+size_t pbit_batch_workspace_bytes(const pbit_problem *probs, const pbit_params *params, int32_t count);
+
+/* Creates a batch in dev_ws (caller-owned device memory, 256-byte aligned, at
+ * least pbit_batch_workspace_bytes).  rounds[i] is member i's round budget
+ * (NULL: unlimited); a member whose budget is spent is skipped by later rounds.
+ * blocks is the persistent grid size (0: one workgroup per resident slot).
+ * Errors as pbit_create_instance; the message names the failing member. */
+pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *params, int32_t count,
+                              const int32_t *rounds, int32_t blocks, void *dev_ws, size_t ws_bytes,
+                              pbit_stream stream, pbit_batch **out);
+
+/* One round (annealing runs and epilogue) of every member with budget left.
+ * Asynchronous on stream. */
+pbit_status pbit_batch_sample_round(pbit_batch *batch, pbit_stream stream);
+
+/* The multiplier step of every member with budget left; uses one unit of
+ * its budget.  Asynchronous on stream. */
+pbit_status pbit_batch_update_lambda(pbit_batch *batch, pbit_stream stream);
+
+/* rounds x (sample_round + update_lambda).  use_graph != 0 records the four
+ * launches of a round once as a HIP graph and replays it; the results are
+ * those of the direct launches.  Asynchronous on stream. */
+pbit_status pbit_batch_run(pbit_batch *batch, int32_t rounds, int32_t use_graph, pbit_stream stream);
+
+/* Member i as an instance handle owned by the batch (do not destroy it):
+ * pbit_get_lambda, pbit_set_lambda, pbit_best_feasible, pbit_round_outputs
+ * and pbit_instance_info apply to it; pbit_sample_round and
+ * pbit_update_lambda on it run that member alone. */
+pbit_status pbit_batch_member(pbit_batch *batch, int32_t index, pbit_instance **member);
+
+/* Copies the remaining round budgets (count values) to host memory;
+ * synchronises stream. */
+pbit_status pbit_batch_rounds_left(pbit_batch *batch, int32_t *rounds_left, pbit_stream stream);
+
+/* Work-queue description: items and persistent workgroups per round. */
+pbit_status pbit_batch_shape(const pbit_batch *batch, int32_t *items, int32_t *blocks, size_t *lds_bytes);
+
+/* Releases the batch, its members and its graph.  Does not synchronise. */
+pbit_status pbit_destroy_batch(pbit_batch *batch);
+
 /* Thread-local message describing the last failing call on this thread. */
 const char *pbit_last_error(void);
 

@@ -73,6 +73,21 @@ EXPORTS = {
     "pbit_destroy_instance": (ctypes.c_int, [ctypes.c_void_p]),
     "pbit_last_error": (ctypes.c_char_p, []),
     "pbit_theta_table": (ctypes.c_int, [ctypes.c_void_p]),
+    "pbit_instance_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "pbit_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "pbit_create_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_batch_sample_round": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_batch_update_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_void_p]),
+    "pbit_batch_member": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "pbit_batch_rounds_left": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_batch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "pbit_destroy_batch": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 _LIB = None
@@ -198,17 +213,96 @@ def pbit_destroy_instance(inst: int) -> None:
     _check(lib().pbit_destroy_instance(inst))
 
 
+def pbit_instance_info(inst: int) -> pbit_plan_info:
+    info = pbit_plan_info()
+    _check(lib().pbit_instance_info(inst, ctypes.byref(info)))
+    return info
+
+
+def pbit_set_tiling(inst: int, waves_per_block: int, lds_resident: int = -1) -> None:
+    _check(lib().pbit_set_tiling(inst, int(waves_per_block), int(lds_resident)))
+
+
+class _MarshalledSet:
+    """C arrays of problems and params for a batch."""
+
+    def __init__(self, probs, pars):
+        self.items = [_Marshalled(p, q) for p, q in zip(probs, pars)]
+        n = len(self.items)
+        self.problems = (pbit_problem * n)(*[m.problem for m in self.items])
+        self.params = (pbit_params * n)(*[m.params for m in self.items])
+        self.count = n
+
+
+def pbit_batch_workspace_bytes(probs, pars) -> int:
+    ms = _MarshalledSet(probs, pars)
+    return int(lib().pbit_batch_workspace_bytes(ms.problems, ms.params, ms.count))
+
+
+def pbit_create_batch(probs, pars, rounds, workspace, blocks: int = 0, stream=None) -> int:
+    ms = _MarshalledSet(probs, pars)
+    rv = None if rounds is None else np.ascontiguousarray(np.asarray(rounds, dtype=np.int32))
+    handle = ctypes.c_void_p()
+    _check(lib().pbit_create_batch(ms.problems, ms.params, ms.count,
+                                   None if rv is None else rv.ctypes.data, int(blocks),
+                                   workspace.data_ptr(), workspace.numel(),
+                                   _stream_handle(stream), ctypes.byref(handle)))
+    return int(handle.value)
+
+
+def pbit_batch_sample_round(batch: int, stream=None) -> None:
+    _check(lib().pbit_batch_sample_round(batch, _stream_handle(stream)))
+
+
+def pbit_batch_update_lambda(batch: int, stream=None) -> None:
+    _check(lib().pbit_batch_update_lambda(batch, _stream_handle(stream)))
+
+
+def pbit_batch_run(batch: int, rounds: int, use_graph: bool = True, stream=None) -> None:
+    _check(lib().pbit_batch_run(batch, int(rounds), 1 if use_graph else 0, _stream_handle(stream)))
+
+
+def pbit_batch_member(batch: int, index: int) -> int:
+    handle = ctypes.c_void_p()
+    _check(lib().pbit_batch_member(batch, int(index), ctypes.byref(handle)))
+    return int(handle.value)
+
+
+def pbit_batch_rounds_left(batch: int, count: int, stream=None) -> np.ndarray:
+    out = np.zeros(count, dtype=np.int32)
+    _check(lib().pbit_batch_rounds_left(batch, out.ctypes.data, _stream_handle(stream)))
+    return out
+
+
+def pbit_batch_shape(batch: int):
+    items, blocks, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(lib().pbit_batch_shape(batch, ctypes.byref(items), ctypes.byref(blocks), ctypes.byref(lds)))
+    return int(items.value), int(blocks.value), int(lds.value)
+
+
+def pbit_destroy_batch(batch: int) -> None:
+    _check(lib().pbit_destroy_batch(batch))
+
+
 class Instance:
     """One compiled instance with its torch-owned workspace on the current device."""
 
-    def __init__(self, prob: Problem, par: Params, stream=None):
+    def __init__(self, prob: Problem, par: Params, stream=None, _member=None):
         import torch
         self.problem, self.params, self.stream = prob, par, stream
-        self.info = pbit_plan(prob, par)
-        # torch's caching allocator hands out blocks aligned to at least 512 bytes
-        self.workspace = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device="cuda")
+        self.owned = _member is None
+        if self.owned:
+            self.info = pbit_plan(prob, par)
+            # torch's caching allocator hands out blocks aligned to at least 512 bytes
+            self.workspace = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device="cuda")
+            self.handle = pbit_create_instance(prob, par, self.workspace, stream)
+        else:
+            self.handle = _member
+            self.info = pbit_instance_info(_member)
         self.outbuf = torch.empty(int(self.info.out_bytes), dtype=torch.uint8, device="cuda")
-        self.handle = pbit_create_instance(prob, par, self.workspace, stream)
+
+    def set_tiling(self, waves_per_block: int, lds_resident: int = -1):
+        pbit_set_tiling(self.handle, waves_per_block, lds_resident)
 
     def sample_round(self):
         pbit_sample_round(self.handle, self.stream)
@@ -247,8 +341,55 @@ class Instance:
         }
 
     def close(self):
-        if self.handle:
+        if self.handle and self.owned:
             pbit_destroy_instance(self.handle)
+        self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A set of instances run together (one persistent launch per round) in one
+    torch-owned workspace.  members[i] is an Instance view of member i (its
+    lambda / residual vectors include any padding constraints)."""
+
+    def __init__(self, probs, pars, rounds=None, blocks: int = 0, stream=None):
+        import torch
+        self.problems, self.params, self.stream = list(probs), list(pars), stream
+        nbytes = pbit_batch_workspace_bytes(self.problems, self.params)
+        if nbytes == 0:
+            # re-run through create for the error message
+            nbytes = 256
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        self.handle = pbit_create_batch(self.problems, self.params, rounds, self.workspace, blocks, stream)
+        self.members = [Instance(p, q, stream, _member=pbit_batch_member(self.handle, i))
+                        for i, (p, q) in enumerate(zip(self.problems, self.params))]
+
+    def sample_round(self):
+        pbit_batch_sample_round(self.handle, self.stream)
+
+    def update_lambda(self):
+        pbit_batch_update_lambda(self.handle, self.stream)
+
+    def run(self, rounds: int, use_graph: bool = True):
+        pbit_batch_run(self.handle, rounds, use_graph, self.stream)
+
+    def rounds_left(self) -> np.ndarray:
+        return pbit_batch_rounds_left(self.handle, len(self.members), self.stream)
+
+    def shape(self):
+        """(work items, persistent workgroups, LDS bytes per workgroup)."""
+        return pbit_batch_shape(self.handle)
+
+    def close(self):
+        if self.handle:
+            for m in self.members:
+                m.handle = 0
+            pbit_destroy_batch(self.handle)
             self.handle = 0
 
     def __del__(self):

@@ -22,6 +22,7 @@ SOURCES = [
     "api.cpp",
     "round_kernels.hip",
     "sweep_quad.hip",
+    "sweep_batch.hip",
     "sweep_linear_a.hip",
     "sweep_linear_b.hip",
     "sweep_linear_c.hip",

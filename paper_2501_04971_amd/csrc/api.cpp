@@ -27,13 +27,26 @@
 
 namespace pbit {
 hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
-hipError_t launch_sweep_linear_a(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
-hipError_t launch_sweep_linear_b(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
-hipError_t launch_sweep_linear_c(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
-hipError_t launch_sweep_linear_d(const DevInstance &d, bool wide, int wpb, hipStream_t stream);
+hipError_t launch_sweep_linear_a(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
+hipError_t launch_sweep_linear_b(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
+hipError_t launch_sweep_linear_c(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
+hipError_t launch_sweep_linear_d(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
 hipError_t launch_round_reduce(const DevInstance &d, hipStream_t stream);
 hipError_t launch_lambda_update(const DevInstance &d, int mode, const int32_t *values,
                                 hipStream_t stream);
+hipError_t launch_round_reduce_batch(const DevInstance *insts, int count, hipStream_t stream);
+hipError_t launch_lambda_update_batch(const DevInstance *insts, int count, int mode, hipStream_t stream);
+hipError_t launch_reset_counter(int *counter, hipStream_t stream);
+hipError_t launch_sweep_batch(const DevInstance *insts, const int4 *items, int n_items, int *counter,
+                              int blocks, size_t lds, hipStream_t stream);
+hipError_t sweep_batch_prepare(size_t lds, int *blocks_per_cu);
+const void *sweep_batch_kernel();
+const void *round_reduce_batch_kernel();
+const void *lambda_update_batch_kernel();
+const void *reset_counter_kernel();
+int reduce_threads();
+int batch_linear_m(int m);
+int batch_variant_code(int variant, int nb, int m);
 }  // namespace pbit
 
 using namespace pbit;
@@ -465,7 +478,16 @@ void fill_plan_info(const Plan &P, pbit_plan_info *out)
     out->out_bytes = o;
 }
 
-int waves_per_block(const Plan &P)
+const size_t kMaxLds = 160 * 1024;
+
+// LDS of the linear kernel with LDS-resident site constants for wpb waves.
+size_t resident_bytes(const Plan &P, int wpb)
+{
+    return (size_t)kThetaBytes + (size_t)(32 * P.words + 32) * 16 + (size_t)P.owords * 32 * P.m * 4 +
+           (size_t)wpb * P.words * kWave * 4;
+}
+
+int waves_per_block_default(const Plan &P)
 {
     if (const char *e = std::getenv("PBIT_WAVES_PER_BLOCK")) {
         const int v = std::atoi(e);
@@ -483,7 +505,31 @@ struct pbit_instance {
     std::vector<unsigned char> upload;
     int device = 0;
     int wpb = 1;
+    int resident = -1;    // linear kernels: 1 LDS-resident constants, 0 global, -1 whichever fits
     bool broken = false;
+    bool member = false;  // owned by a batch
+};
+
+struct pbit_batch {
+    std::vector<pbit_instance *> members;
+    std::vector<DevInstance> dev;      // host image of the device record array
+    std::vector<int4> items;           // host image of the work queue
+    std::vector<int32_t> rounds;       // initial budgets
+    DevInstance *d_insts = nullptr;
+    int4 *d_items = nullptr;
+    int *d_counter = nullptr;
+    int32_t *d_rounds = nullptr;
+    int blocks = 0;
+    size_t lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool broken = false;
+    ~pbit_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (pbit_instance *m : members) delete m;
+    }
 };
 
 namespace {
@@ -503,38 +549,9 @@ pbit_status check_live(pbit_instance *inst)
 
 }  // namespace
 
-extern "C" {
-
-const char *pbit_last_error(void) { return g_error.c_str(); }
-
-pbit_status pbit_theta_table(int32_t *theta)
-{
-    if (!theta) return fail(PBIT_EINVAL, "null output");
-    std::vector<int32_t> t;
-    if (!make_theta(t)) return fail(PBIT_ERANGE, "threshold table rounding undecidable");
-    std::memcpy(theta, t.data(), t.size() * 4);
-    return PBIT_OK;
-}
-
-pbit_status pbit_plan(const pbit_problem *prob, const pbit_params *par, pbit_plan_info *out)
-{
-    if (!out) return fail(PBIT_EINVAL, "null output");
-    Plan P;
-    const pbit_status st = make_plan(prob, par, P);
-    if (st != PBIT_OK) return st;
-    fill_plan_info(P, out);
-    return PBIT_OK;
-}
-
-size_t pbit_workspace_bytes(const pbit_problem *prob, const pbit_params *par)
-{
-    Plan P;
-    if (make_plan(prob, par, P) != PBIT_OK) return 0;
-    return P.L.total;
-}
-
-pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *par, void *dev_ws,
-                                 size_t ws_bytes, pbit_stream stream, pbit_instance **out)
+namespace {
+pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *dev_ws, size_t ws_bytes,
+                        pbit_stream stream, pbit_instance **out)
 {
     if (!out) return fail(PBIT_EINVAL, "null output handle");
     pbit_instance *inst = new (std::nothrow) pbit_instance();
@@ -630,7 +647,7 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
     d.seed_lo = (uint32_t)P.seed;
     d.seed_hi = (uint32_t)(P.seed >> 32);
     d.inst_id = P.inst;
-    inst->wpb = waves_per_block(P);
+    inst->wpb = waves_per_block_default(P);
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     e = hipMemcpyAsync(dev_ws, inst->upload.data(), L.upload_end, hipMemcpyHostToDevice, s);
@@ -643,6 +660,172 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
     }
     *out = inst;
     return PBIT_OK;
+}
+
+
+// Multi-knapsack members are padded to a constraint count with a batch body.
+struct PaddedProblem {
+    pbit_problem prob{};
+    std::vector<int32_t> weight;
+    std::vector<int64_t> capacity;
+};
+
+struct BatchSizes {
+    std::vector<PaddedProblem> padded;
+    std::vector<size_t> member_bytes, off_member;
+    size_t off_insts = 0, off_items = 0, off_counter = 0, off_rounds = 0, total = 0;
+};
+
+pbit_status batch_sizes(const pbit_problem *probs, const pbit_params *params, int count, BatchSizes &z)
+{
+    if (!probs || !params || count < 1) return fail(PBIT_EINVAL, "null arrays or count < 1");
+    z.padded.resize(count);
+    size_t items = 0;
+    for (int i = 0; i < count; ++i) {
+        PaddedProblem &pp = z.padded[i];
+        pp.prob = probs[i];
+        const pbit_problem &p = probs[i];
+        if (p.kind == PBIT_MKP && p.m >= 1 && p.m <= kMaxM && p.n >= 1 && p.weight && p.capacity) {
+            const int mb = batch_linear_m(p.m);
+            if (mb != p.m) {
+                pp.weight.assign((size_t)mb * p.n, 0);
+                std::memcpy(pp.weight.data(), p.weight, (size_t)p.m * p.n * 4);
+                pp.capacity.assign(mb, 0);
+                std::memcpy(pp.capacity.data(), p.capacity, (size_t)p.m * 8);
+                pp.prob.m = mb;
+                pp.prob.weight = pp.weight.data();
+                pp.prob.capacity = pp.capacity.data();
+            }
+        }
+        Plan P;
+        pbit_status st = make_plan(&pp.prob, &params[i], P);
+        if (st != PBIT_OK) {
+            g_error = "member " + std::to_string(i) + ": " + g_error;
+            return st;
+        }
+        if (batch_variant_code(P.variant, P.nb, P.m) < 0 ||
+            (P.variant != kQuad && resident_bytes(P, 4) > kMaxLds))
+            return fail(PBIT_ERANGE, "member " + std::to_string(i) + ": no batch body for this instance shape");
+        z.member_bytes.push_back(P.L.total);
+        items += (size_t)(P.R + 255) / 256;
+    }
+    size_t o = 0;
+    auto put = [&o](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    z.off_insts = put((size_t)count * sizeof(DevInstance));
+    z.off_items = put(items * sizeof(int4));
+    z.off_counter = put(4);
+    z.off_rounds = put((size_t)count * 4);
+    for (int i = 0; i < count; ++i) z.off_member.push_back(put(z.member_bytes[i]));
+    z.total = o;
+    return PBIT_OK;
+}
+
+pbit_status check_batch(pbit_batch *b)
+{
+    if (!b) return fail(PBIT_EINVAL, "null batch");
+    if (b->broken) return fail(PBIT_ESTATE, "batch is unusable after a device error");
+    return PBIT_OK;
+}
+
+pbit_status batch_error(pbit_batch *b, hipError_t e, const char *what)
+{
+    b->broken = true;
+    for (pbit_instance *m : b->members) m->broken = true;
+    return fail(PBIT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// The four launches of one batch round as a graph of kernel nodes in a chain
+// (the work-queue counter is cleared by a kernel, not a memset node).
+hipError_t build_round_graph(pbit_batch *b)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    DevInstance *insts = b->d_insts;
+    int4 *items = b->d_items;
+    int *counter = b->d_counter;
+    int n_items = (int)b->items.size();
+    int mode = 1;
+    void *a_reset[] = {&counter};
+    void *a_sweep[] = {&insts, &items, &n_items, &counter};
+    void *a_reduce[] = {&insts};
+    void *a_lambda[] = {&insts, &mode};
+    const int count = (int)b->members.size();
+    struct Node {
+        const void *func;
+        dim3 grid, block;
+        size_t lds;
+        void **args;
+    } nodes[4] = {
+        {reset_counter_kernel(), dim3(1), dim3(64), 0, a_reset},
+        {sweep_batch_kernel(), dim3(b->blocks), dim3(256), b->lds, a_sweep},
+        {round_reduce_batch_kernel(), dim3(count), dim3(reduce_threads()), 0, a_reduce},
+        {lambda_update_batch_kernel(), dim3(count), dim3(256), 0, a_lambda},
+    };
+    hipGraphNode_t prev = nullptr;
+    for (const Node &nd : nodes) {
+        hipKernelNodeParams p{};
+        p.func = const_cast<void *>(nd.func);
+        p.gridDim = nd.grid;
+        p.blockDim = nd.block;
+        p.sharedMemBytes = (unsigned)nd.lds;
+        p.kernelParams = nd.args;
+        p.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (e != hipSuccess) break;
+        prev = node;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        b->exec = nullptr;
+        return e;
+    }
+    b->graph = g;
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pbit_last_error(void) { return g_error.c_str(); }
+
+pbit_status pbit_theta_table(int32_t *theta)
+{
+    if (!theta) return fail(PBIT_EINVAL, "null output");
+    std::vector<int32_t> t;
+    if (!make_theta(t)) return fail(PBIT_ERANGE, "threshold table rounding undecidable");
+    std::memcpy(theta, t.data(), t.size() * 4);
+    return PBIT_OK;
+}
+
+pbit_status pbit_plan(const pbit_problem *prob, const pbit_params *par, pbit_plan_info *out)
+{
+    if (!out) return fail(PBIT_EINVAL, "null output");
+    Plan P;
+    const pbit_status st = make_plan(prob, par, P);
+    if (st != PBIT_OK) return st;
+    fill_plan_info(P, out);
+    return PBIT_OK;
+}
+
+size_t pbit_workspace_bytes(const pbit_problem *prob, const pbit_params *par)
+{
+    Plan P;
+    if (make_plan(prob, par, P) != PBIT_OK) return 0;
+    return P.L.total;
+}
+
+pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *par, void *dev_ws,
+                                 size_t ws_bytes, pbit_stream stream, pbit_instance **out)
+{
+    return create_impl(prob, par, dev_ws, ws_bytes, stream, out);
 }
 
 pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
@@ -658,10 +841,12 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
             break;
         default: {
             const bool wide = inst->plan.variant == kLinearWide;
-            if (d.m <= 6) e = launch_sweep_linear_a(d, wide, inst->wpb, s);
-            else if (d.m <= 12) e = launch_sweep_linear_b(d, wide, inst->wpb, s);
-            else if (d.m <= 20) e = launch_sweep_linear_c(d, wide, inst->wpb, s);
-            else e = launch_sweep_linear_d(d, wide, inst->wpb, s);
+            const bool res = inst->resident == 1 ||
+                             (inst->resident < 0 && resident_bytes(inst->plan, inst->wpb) <= kMaxLds);
+            if (d.m <= 6) e = launch_sweep_linear_a(d, wide, inst->wpb, res, s);
+            else if (d.m <= 12) e = launch_sweep_linear_b(d, wide, inst->wpb, res, s);
+            else if (d.m <= 20) e = launch_sweep_linear_c(d, wide, inst->wpb, res, s);
+            else e = launch_sweep_linear_d(d, wide, inst->wpb, res, s);
         }
     }
     if (e == hipSuccess) e = launch_round_reduce(d, s);
@@ -759,7 +944,205 @@ pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes,
 pbit_status pbit_destroy_instance(pbit_instance *inst)
 {
     if (!inst) return fail(PBIT_EINVAL, "null instance");
+    if (inst->member) return fail(PBIT_EINVAL, "instance is a batch member; destroy the batch");
     delete inst;
+    return PBIT_OK;
+}
+
+pbit_status pbit_instance_info(const pbit_instance *inst, pbit_plan_info *out)
+{
+    if (!inst || !out) return fail(PBIT_EINVAL, "null instance or output");
+    fill_plan_info(inst->plan, out);
+    return PBIT_OK;
+}
+
+pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_t lds_resident)
+{
+    pbit_status st = check_live(inst);
+    if (st != PBIT_OK) return st;
+    const bool quad = inst->plan.variant == kQuad;
+    const int wpb = waves_per_block == 0 ? waves_per_block_default(inst->plan) : waves_per_block;
+    const bool ok = quad ? (wpb == 1 || wpb == 4) : (wpb >= 1 && wpb <= 4);
+    if (!ok) return fail(PBIT_EINVAL, "waves per block must be 1 or 4 (quadratic) or 1..4 (linear)");
+    if (lds_resident < -1 || lds_resident > 1) return fail(PBIT_EINVAL, "lds_resident must be -1, 0 or 1");
+    if (!quad && lds_resident == 1 && resident_bytes(inst->plan, wpb) > kMaxLds)
+        return fail(PBIT_ERANGE, "site constants do not fit LDS at this tiling");
+    inst->wpb = wpb;
+    inst->resident = quad ? -1 : lds_resident;
+    return PBIT_OK;
+}
+
+size_t pbit_batch_workspace_bytes(const pbit_problem *probs, const pbit_params *params, int32_t count)
+{
+    BatchSizes z;
+    if (batch_sizes(probs, params, count, z) != PBIT_OK) return 0;
+    return z.total;
+}
+
+pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *params, int32_t count,
+                              const int32_t *rounds, int32_t blocks, void *dev_ws, size_t ws_bytes,
+                              pbit_stream stream, pbit_batch **out)
+{
+    if (!out) return fail(PBIT_EINVAL, "null output handle");
+    if (blocks < 0) return fail(PBIT_EINVAL, "blocks must be >= 0");
+    BatchSizes z;
+    pbit_status st = batch_sizes(probs, params, count, z);
+    if (st != PBIT_OK) return st;
+    if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0 || ws_bytes < z.total)
+        return fail(PBIT_EWORKSPACE, "workspace missing, misaligned or smaller than pbit_batch_workspace_bytes");
+    if (rounds)
+        for (int i = 0; i < count; ++i)
+            if (rounds[i] < 0) return fail(PBIT_EINVAL, "round budgets must be >= 0");
+
+    pbit_batch *b = new (std::nothrow) pbit_batch();
+    if (!b) return fail(PBIT_EINVAL, "host allocation failed");
+    unsigned char *base = static_cast<unsigned char *>(dev_ws);
+    b->d_insts = reinterpret_cast<DevInstance *>(base + z.off_insts);
+    b->d_items = reinterpret_cast<int4 *>(base + z.off_items);
+    b->d_counter = reinterpret_cast<int *>(base + z.off_counter);
+    b->d_rounds = reinterpret_cast<int32_t *>(base + z.off_rounds);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    struct Cost {
+        int64_t cost;
+        int4 item;
+    };
+    std::vector<Cost> q;
+    for (int i = 0; i < count; ++i) {
+        pbit_instance *m = nullptr;
+        st = create_impl(&z.padded[i].prob, &params[i], base + z.off_member[i], z.member_bytes[i], stream, &m);
+        if (st != PBIT_OK) {
+            g_error = "member " + std::to_string(i) + ": " + g_error;
+            delete b;  // members created so far are released by the destructor
+            return st;
+        }
+        m->member = true;
+        m->dev.rounds_left = b->d_rounds + i;
+        b->members.push_back(m);
+        b->dev.push_back(m->dev);
+        const Plan &P = m->plan;
+        const int code = batch_variant_code(P.variant, P.nb, P.m);
+        const int64_t per_visit = P.variant == kQuad ? 96 + 8 * P.nb : 64 + 6 * P.m;
+        const int64_t cost = (int64_t)P.T * P.n_ext * per_visit;
+        for (int r0 = 0; r0 < P.R; r0 += 256)
+            q.push_back({cost, make_int4(i, r0, code, (int)std::min<int64_t>(cost >> 16, INT32_MAX))});
+        const size_t need = P.variant == kQuad
+                                ? (size_t)kThetaBytes + (size_t)P.nb * 1024 + (size_t)2048 * (P.nb + 1)
+                                : resident_bytes(P, 4);
+        b->lds = std::max(b->lds, need);
+        b->rounds.push_back(rounds ? rounds[i] : INT32_MAX);
+    }
+    std::stable_sort(q.begin(), q.end(), [](const Cost &x, const Cost &y) { return x.cost > y.cost; });
+    for (const Cost &c : q) b->items.push_back(c.item);
+
+    int per_cu = 0, cus = 0, dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = sweep_batch_prepare(b->lds, &per_cu);
+    if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
+    const int n_items = (int)b->items.size();
+    b->blocks = blocks > 0 ? blocks : std::min(n_items, cus * per_cu);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_insts, b->dev.data(), b->dev.size() * sizeof(DevInstance), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_items, b->items.data(), b->items.size() * sizeof(int4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_rounds, b->rounds.data(), b->rounds.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_reset_counter(b->d_counter, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        pbit_status r = device_error(nullptr, e, "batch upload failed");
+        delete b;
+        return r;
+    }
+    *out = b;
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_sample_round(pbit_batch *b, pbit_stream stream)
+{
+    pbit_status st = check_batch(b);
+    if (st != PBIT_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int count = (int)b->members.size();
+    hipError_t e = launch_reset_counter(b->d_counter, s);
+    if (e == hipSuccess)
+        e = launch_sweep_batch(b->d_insts, b->d_items, (int)b->items.size(), b->d_counter, b->blocks, b->lds, s);
+    if (e == hipSuccess) e = launch_round_reduce_batch(b->d_insts, count, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return batch_error(b, e, "batch sample_round launch failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_update_lambda(pbit_batch *b, pbit_stream stream)
+{
+    pbit_status st = check_batch(b);
+    if (st != PBIT_OK) return st;
+    hipError_t e = launch_lambda_update_batch(b->d_insts, (int)b->members.size(), 1,
+                                              reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return batch_error(b, e, "batch update_lambda launch failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_run(pbit_batch *b, int32_t rounds, int32_t use_graph, pbit_stream stream)
+{
+    pbit_status st = check_batch(b);
+    if (st != PBIT_OK) return st;
+    if (rounds < 0) return fail(PBIT_EINVAL, "rounds must be >= 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!use_graph) {
+        for (int k = 0; k < rounds; ++k) {
+            st = pbit_batch_sample_round(b, stream);
+            if (st == PBIT_OK) st = pbit_batch_update_lambda(b, stream);
+            if (st != PBIT_OK) return st;
+        }
+        return PBIT_OK;
+    }
+    if (!b->exec) {
+        hipError_t e = build_round_graph(b);
+        if (e != hipSuccess) return batch_error(b, e, "building the round graph failed");
+    }
+    for (int k = 0; k < rounds; ++k) {
+        hipError_t e = hipGraphLaunch(b->exec, s);
+        if (e != hipSuccess) return batch_error(b, e, "graph launch failed");
+    }
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_member(pbit_batch *b, int32_t index, pbit_instance **member)
+{
+    if (!b || !member) return fail(PBIT_EINVAL, "null batch or output");
+    if (index < 0 || index >= (int)b->members.size()) return fail(PBIT_EINVAL, "member index out of range");
+    *member = b->members[index];
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_rounds_left(pbit_batch *b, int32_t *rounds_left, pbit_stream stream)
+{
+    pbit_status st = check_batch(b);
+    if (st != PBIT_OK) return st;
+    if (!rounds_left) return fail(PBIT_EINVAL, "null output");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(rounds_left, b->d_rounds, b->members.size() * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return batch_error(b, e, "rounds_left failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_shape(const pbit_batch *b, int32_t *items, int32_t *blocks, size_t *lds_bytes)
+{
+    if (!b) return fail(PBIT_EINVAL, "null batch");
+    if (items) *items = (int32_t)b->items.size();
+    if (blocks) *blocks = b->blocks;
+    if (lds_bytes) *lds_bytes = b->lds;
+    return PBIT_OK;
+}
+
+pbit_status pbit_destroy_batch(pbit_batch *b)
+{
+    if (!b) return fail(PBIT_EINVAL, "null batch");
+    delete b;
     return PBIT_OK;
 }
 

@@ -173,6 +173,11 @@ __global__ void reset_counter(int *counter)
     if (threadIdx.x == 0) *counter = 0;
 }
 
+const void *round_reduce_batch_kernel() { return reinterpret_cast<const void *>(&round_reduce_batch); }
+const void *lambda_update_batch_kernel() { return reinterpret_cast<const void *>(&lambda_update_batch); }
+const void *reset_counter_kernel() { return reinterpret_cast<const void *>(&reset_counter); }
+int reduce_threads() { return kReduceThreads; }
+
 hipError_t launch_round_reduce_batch(const DevInstance *insts, int count, hipStream_t stream)
 {
     void *args[] = {&insts};

@@ -35,6 +35,45 @@ __device__ __forceinline__ int64_t constraint_field(const int32_t *ac, const int
     return (int64_t)dd * k2;
 }
 
+// Round epilogue of one replica: profit of the original bits, feasible iff
+// g_k <= slack_k for every k (i.e. the original inequality holds), final state
+// words (slack bits merged in) and residuals.
+template <int M>
+__device__ __forceinline__ void linear_score(const DevInstance &d, int r, uint32_t *xl, int lane,
+                                             const int32_t (&g)[M], const uint32_t (&sk)[M])
+{
+    const bool live = r < d.R;
+    const int n = d.n;
+    int64_t profit = 0;
+    for (int blk = 0; blk < d.owords; ++blk) {
+        const uint32_t xw = xl[blk * kWave + lane];
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+            const int i = blk * 32 + s;
+            if (i < n && ((xw >> s) & 1u)) profit += d.hprof[i];
+        }
+    }
+    bool feasible = true;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        feasible = feasible && (g[k] <= (int32_t)sk[k]);
+        const int off = d.slack_off[k];
+        const int Qk = d.slack_q[k];
+        if (Qk > 0) {
+            const int w0 = off >> 5, b0 = off & 31;
+            xl[w0 * kWave + lane] |= sk[k] << b0;
+            if (b0 + Qk > 32) xl[(w0 + 1) * kWave + lane] |= sk[k] >> (32 - b0);
+        }
+    }
+    if (live) {
+        for (int w = 0; w < d.words; ++w) d.rx[(int64_t)r * d.words + w] = xl[w * kWave + lane];
+#pragma unroll
+        for (int k = 0; k < M; ++k) d.rg[(int64_t)r * d.m + k] = g[k];
+        d.rprofit[r] = profit;
+        d.rfeas[r] = feasible ? 1 : 0;
+    }
+}
+
 // LDS bytes of linear_run for a workgroup of wpb waves and `words` state words.
 inline size_t linear_lds_bytes(int wpb, int words)
 {
@@ -167,50 +206,160 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
         }
     }
 
-    // score: profit of the original bits, feasible iff g_k <= slack_k for all k
-    const bool live = r < d.R;
-    int64_t profit = 0;
-    for (int blk = 0; blk < d.owords; ++blk) {
-        const uint32_t xw = xl[blk * kWave + lane];
-#pragma unroll
-        for (int s = 0; s < 32; ++s) {
-            const int i = blk * 32 + s;
-            if (i < n && ((xw >> s) & 1u)) profit += d.hprof[i];
-        }
-    }
-    bool feasible = true;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        feasible = feasible && (g[k] <= (int32_t)sk[k]);
-        const int off = d.slack_off[k];
-        const int Qk = d.slack_q[k];
-        if (Qk > 0) {
-            const int w0 = off >> 5, b0 = off & 31;
-            xl[w0 * kWave + lane] |= sk[k] << b0;
-            if (b0 + Qk > 32) xl[(w0 + 1) * kWave + lane] |= sk[k] >> (32 - b0);
-        }
-    }
-    if (live) {
-        for (int w = 0; w < d.words; ++w) d.rx[(int64_t)r * d.words + w] = xl[w * kWave + lane];
-#pragma unroll
-        for (int k = 0; k < M; ++k) d.rg[(int64_t)r * d.m + k] = g[k];
-        d.rprofit[r] = profit;
-        d.rfeas[r] = feasible ? 1 : 0;
-    }
+    linear_score<M>(d, r, xl, lane, g, sk);
 }
 
+// LDS bytes of linear_run_lds: the threshold table, the field constants
+// (K0, K1) of every site record, the coefficient rows of the original items
+// and the state words of each wave.
+inline size_t linear_lds_resident_bytes(int wpb, int words, int owords, int m)
+{
+    return (size_t)kThetaBytes + (size_t)(32 * words + 32) * 16 + (size_t)owords * 32 * m * 4 +
+           (size_t)wpb * words * kWave * 4;
+}
+
+// Residual dot a_i.g from LDS coefficients (same value in every lane), summed in
+// up to four independent partial sums so that the chain that waits on the last
+// flip stays short.
 template <int M, bool WIDE>
+__device__ __forceinline__ int64_t residual_dot(const int32_t *a, const int32_t (&g)[M])
+{
+    constexpr int P = M < 4 ? M : 4;
+    if (WIDE) {
+        int64_t part[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) part[p] = (int64_t)a[p] * (int64_t)g[p];
+#pragma unroll
+        for (int k = P; k < M; ++k) part[k % P] += (int64_t)a[k] * (int64_t)g[k];
+        int64_t t = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) t += part[p];
+        return t;
+    }
+    int32_t part[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) part[p] = __mul24(a[p], g[p]);
+#pragma unroll
+    for (int k = P; k < M; ++k) part[k % P] += __mul24(a[k], g[k]);
+    int32_t t = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) t += part[p];
+    return t;
+}
+
+// The same annealing run with every per-site constant resident in LDS and each
+// visit computed directly from the current residuals: field, threshold index,
+// table lookup, decision, O(M) residual update.  No scalar-memory loads in the
+// sweep, so waits on LDS never wait on scalar loads.  The host uses it whenever
+// linear_lds_resident_bytes fits a workgroup.
+template <int M, bool WIDE>
+__device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, unsigned char *smem)
+{
+    const int words = d.words, owords = d.owords;
+    const int n_rec = 32 * words + 32;
+    int32_t *th = reinterpret_cast<int32_t *>(smem);
+    int64_t *kr = reinterpret_cast<int64_t *>(smem + kThetaBytes);
+    int32_t *ac = reinterpret_cast<int32_t *>(smem + kThetaBytes + (size_t)n_rec * 16);
+    const int lane = threadIdx.x & 63;
+    const int wave_in_block = threadIdx.x >> 6;
+    uint32_t *xl = reinterpret_cast<uint32_t *>(smem + kThetaBytes + (size_t)n_rec * 16 +
+                                                (size_t)owords * 32 * M * 4) +
+                   wave_in_block * words * kWave;
+
+    for (int e = threadIdx.x; e < kThetaLen; e += blockDim.x) th[e] = d.theta[e];
+    for (int e = threadIdx.x; e < n_rec; e += blockDim.x) {
+        kr[2 * e] = d.site[4 * e];
+        kr[2 * e + 1] = d.site[4 * e + 1];
+    }
+    for (int e = threadIdx.x; e < owords * 32 * M; e += blockDim.x) ac[e] = d.acol[e];
+    for (int w = 0; w < words; ++w) xl[w * kWave + lane] = 0u;
+    __syncthreads();
+
+    const int r = rbase + threadIdx.x;
+    const uint32_t kround = (uint32_t)d.round_k[0];
+    const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
+    const int n = d.n;
+    const int32_t negk2 = -d.k2;
+    const int32_t ish = d.ish, hclo = d.hclo, hchi = d.hchi;
+    const int64_t irnd = d.irnd;
+
+    int32_t g[M];
+    uint32_t sk[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        g[k] = -(int32_t)d.b[k];
+        sk[k] = 0u;
+    }
+
+    for (int t = 0; t < d.T; ++t) {
+        const int32_t Bt = d.Btab[t];
+        const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
+        for (int blk = 0; blk < owords; ++blk) {
+            uint32_t xw = xl[blk * kWave + lane];
+            const int rem = n - blk * 32;  // original items in this word (the rest are not visited here)
+            uint32_t rnd[4];
+#pragma unroll
+            for (int s = 0; s < 32; ++s) {
+                const int i = blk * 32 + s;
+                if ((s & 3) == 0)
+                    philox_block(cbase + (uint32_t)(i >> 2), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
+                const uint32_t xo = (xw >> s) & 1u;
+                const int32_t *a = ac + i * M;
+                const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
+                const int64_t dd = residual_dot<M, WIDE>(a, g);
+                const int64_t Z = WIDE ? K + dd * (int64_t)negk2 : K + (int64_t)(int32_t)dd * negk2;
+                const uint32_t thr = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf] &
+                                     (s < rem ? 0xFFFFFFFFu : 0u);
+                const uint32_t xn = (rnd[s & 3] >> 8) < thr ? 1u : 0u;
+                const int32_t delta = (int32_t)xn - (int32_t)xo;
+#pragma unroll
+                for (int k = 0; k < M; ++k) g[k] += WIDE ? delta * a[k] : __mul24(delta, a[k]);
+                xw = (xw & ~(1u << s)) | (xn << s);
+            }
+            xl[blk * kWave + lane] = xw;
+        }
+        // slack bits, constraint by constraint (a = 2^q e_k: the field needs g_k only)
+        uint32_t rnd[4] = {0u, 0u, 0u, 0u};
+        int grp = -1;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int off = d.slack_off[k];
+            const int Qk = d.slack_q[k];
+            for (int q = 0; q < Qk; ++q) {
+                const int i = off + q;
+                if ((i >> 2) != grp) {
+                    grp = i >> 2;
+                    philox_block(cbase + (uint32_t)grp, kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
+                }
+                const uint32_t xo = (sk[k] >> q) & 1u;
+                const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
+                const int64_t Z = K + (((int64_t)g[k] * negk2) << q);
+                const uint32_t thr = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
+                const int sel = i & 3;
+                const uint32_t word = sel == 0 ? rnd[0] : sel == 1 ? rnd[1] : sel == 2 ? rnd[2] : rnd[3];
+                const uint32_t xn = (word >> 8) < thr ? 1u : 0u;
+                g[k] += ((int32_t)xn - (int32_t)xo) << q;
+                sk[k] = (sk[k] & ~(1u << q)) | (xn << q);
+            }
+        }
+    }
+    linear_score<M>(d, r, xl, lane, g, sk);
+}
+
+template <int M, bool WIDE, bool RES>
 __global__ __launch_bounds__(256) void sweep_linear(const DevInstance d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    linear_run<M, WIDE>(d, blockIdx.x * blockDim.x, smem);
+    if (RES) linear_run_lds<M, WIDE>(d, blockIdx.x * blockDim.x, smem);
+    else linear_run<M, WIDE>(d, blockIdx.x * blockDim.x, smem);
 }
 
 inline hipError_t launch_linear_kernel(const void *kern, const DevInstance &d, int waves_per_block,
-                                       hipStream_t stream)
+                                       bool resident, hipStream_t stream)
 {
     const int wpb = waves_per_block < 1 ? 1 : waves_per_block;
-    const size_t lds = linear_lds_bytes(wpb, d.words);
+    const size_t lds = resident ? linear_lds_resident_bytes(wpb, d.words, d.owords, d.m)
+                                : linear_lds_bytes(wpb, d.words);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int waves = (d.R + kWave - 1) / kWave;
@@ -223,6 +372,8 @@ inline hipError_t launch_linear_kernel(const void *kern, const DevInstance &d, i
 
 #define PBIT_LINEAR_CASE(mm)                                                                \
     case mm:                                                                                \
-        kern = wide ? reinterpret_cast<const void *>(&sweep_linear<mm, true>)              \
-                    : reinterpret_cast<const void *>(&sweep_linear<mm, false>);            \
+        kern = resident ? (wide ? reinterpret_cast<const void *>(&sweep_linear<mm, true, true>) \
+                                : reinterpret_cast<const void *>(&sweep_linear<mm, false, true>)) \
+                        : (wide ? reinterpret_cast<const void *>(&sweep_linear<mm, true, false>) \
+                                : reinterpret_cast<const void *>(&sweep_linear<mm, false, false>)); \
         break;

@@ -3,7 +3,7 @@
 
 namespace pbit {
 
-hipError_t launch_sweep_linear_d(const DevInstance &d, bool wide, int waves_per_block,
+hipError_t launch_sweep_linear_d(const DevInstance &d, bool wide, int waves_per_block, bool resident,
                                    hipStream_t stream)
 {
     const void *kern = nullptr;
@@ -12,7 +12,7 @@ hipError_t launch_sweep_linear_d(const DevInstance &d, bool wide, int waves_per_
         default:
             return hipErrorInvalidValue;
     }
-    return launch_linear_kernel(kern, d, waves_per_block, stream);
+    return launch_linear_kernel(kern, d, waves_per_block, resident, stream);
 }
 
 }  // namespace pbit

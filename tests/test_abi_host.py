@@ -105,3 +105,28 @@ def test_null_workspace_is_rejected_before_any_device_call(lib):
     assert st == B.PBIT_EWORKSPACE and h.value is None
     assert lib.pbit_sample_round(None, None) == B.PBIT_EINVAL
     assert b"null instance" in lib.pbit_last_error()
+
+
+def test_batch_sizes_and_member_errors(lib):
+    """Batch workspace covers every member's own workspace plus the queue; a bad
+    member is named in the message; constraint counts without a batch body are
+    padded (their plan is the padded one, with no extra slack bits)."""
+    members = [G.workload(3, i) for i in range(6)]
+    probs = [p for p, _, _ in members]
+    pars = [q for _, q, _ in members]
+    total = B.pbit_batch_workspace_bytes(probs, pars)
+    assert total > sum(B.pbit_workspace_bytes(p, q) for p, q in zip(probs, pars))
+    mk = G.mkp(60, 7, G.rng_for(940, 0))
+    par = G.Params(replicas=64, sweeps=10, beta=Fraction(50), alpha=Fraction(5))
+    assert B.pbit_batch_workspace_bytes([mk], [par]) >= B.pbit_workspace_bytes(mk, par)
+    padded = G.Problem(G.KIND_MKP, mk.profit, np.vstack([mk.weight, np.zeros((1, 60), np.int64)]),
+                       np.concatenate([mk.capacity, [0]]), mk.density)
+    assert B.pbit_plan(padded, par).n_ext == B.pbit_plan(mk, par).n_ext
+    bad = G.Problem(7, probs[0].profit, probs[0].weight, probs[0].capacity, probs[0].density)
+    assert B.pbit_batch_workspace_bytes([probs[1], bad], pars[:2]) == 0
+    st = lib.pbit_create_batch(None, None, 0, None, 0, None, 0, None, ctypes.byref(ctypes.c_void_p()))
+    assert st == B.PBIT_EINVAL
+    ms = B._MarshalledSet([probs[1], bad], pars[:2])
+    h = ctypes.c_void_p()
+    st = lib.pbit_create_batch(ms.problems, ms.params, 2, None, 0, None, 0, None, ctypes.byref(h))
+    assert st == B.PBIT_EINVAL and b"member 1" in lib.pbit_last_error()

@@ -178,3 +178,38 @@ def test_full_size_workload1_round0(need_gpu):
     prob, par, _ = G.workload(1, 0)
     say("[parity] workload 1 full size, round 0")
     _spot_check_round0(prob, par, [0, 5, 511, 1023])
+
+
+@pytest.mark.parametrize("case", ["qkp97", "mkp100x5", "mkp100x30", "mkp120x12wide"])
+def test_every_tiling_is_bit_identical(need_gpu, case):
+    """Each launch layout (waves per workgroup; for the linear kernel, site
+    constants staged in LDS or read from global memory) gives the oracle's round."""
+    if case == "qkp97":
+        prob = G.qkp(97, Fraction(3, 4), G.rng_for(950, 0))
+        par = G.Params(replicas=300, sweeps=30, beta=Fraction(5), eta=Fraction(20))
+        layouts = [(1, -1), (4, -1)]
+    else:
+        if case == "mkp120x12wide":
+            rng = G.rng_for(950, 3)
+            a = rng.integers(1, 20000, size=(12, 120), dtype=np.int64)
+            prob = G.Problem(G.KIND_MKP, rng.integers(1, 200, size=120), a, a.sum(axis=1) // 4,
+                             Fraction(0))
+        else:
+            m = 5 if case == "mkp100x5" else 30
+            prob = G.mkp(100, m, G.rng_for(950, m))
+        par = G.Params(replicas=300, sweeps=25, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
+        layouts = [(1, 0), (1, 1), (2, 1), (3, 0), (4, 1), (4, 0)]
+    ref = O.saim(prob, par, 2, nthreads=NTHREADS)
+    prog = ref["program"]
+    for wpb, res in layouts:
+        say(f"[tiling] {case} waves/block={wpb} lds_resident={res}")
+        inst = B.Instance(prob, par)
+        inst.set_tiling(wpb, res)
+        for k in range(2):
+            lam = inst.get_lambda()
+            inst.sample_round()
+            out = inst.round_outputs()
+            inst.update_lambda()
+            out["lq"] = lam
+            assert_round_equal(prog, ref["rounds"][k], out, k)
+        inst.close()
