@@ -243,8 +243,85 @@ pbit_status pbit_batch_rounds_left(pbit_batch *batch, int32_t *rounds_left, pbit
 /* Work-queue description: items and persistent workgroups per round. */
 pbit_status pbit_batch_shape(const pbit_batch *batch, int32_t *items, int32_t *blocks, size_t *lds_bytes);
 
+/* Sets every member's lambda_q from lambda_q (device memory, int32
+ * [count][32], member i's values at i*32 + k; entries beyond a member's m are
+ * ignored), clamped to +-lq_max, e.g. the learned starting point written by
+ * pbit_net_to_lambda.  Asynchronous on stream. */
+pbit_status pbit_batch_set_lambdas(pbit_batch *batch, const int32_t *lambda_q, pbit_stream stream);
+
+/* Writes one 160-byte record per member to dev_out (device memory), ordered
+ * on stream: int64 best feasible profit; int32 its round, 1 if any feasible
+ * sample exists, rounds done, feasible samples in the last round, two zero
+ * words; int32 lambda_q[32] (zero beyond m). */
+pbit_status pbit_batch_snapshot(pbit_batch *batch, void *dev_out, pbit_stream stream);
+
 /* Releases the batch, its members and its graph.  Does not synchronise. */
 pbit_status pbit_destroy_batch(pbit_batch *batch);
+
+/* ---- Learned starting multipliers ---------------------------------------
+ * A set encoder predicts lambda_0 for each constraint of an instance, to start
+ * Algorithm 1 near the value its multipliers settle to (the paper starts from
+ * lambda_0 = 0).  One set per (instance, constraint k), one element per
+ * original variable i with features (bf16, 16 per element, four used)
+ *   rho_i/(s_f n), n a_ki/b_k, n mean_k' a_k'i/b_k', h_i/s_f
+ * where rho_i = h_i + sum_j W_ij, and a context of six values per set (bf16,
+ * 16 stored): log(N_ext)/8, d, P/N_ext, beta_max/50, M/32, kind.
+ * Network: phi = Linear(16,128)-ReLU-Linear(128,128)-ReLU per element, mean over
+ * the set, head = Linear(144,128)-ReLU-Linear(128,1) on [pooled, context] -> t.
+ * lambda_q,k = round_half_away(t * scale_k), scale_k = 256 rho_bar_k s_g / s_f,
+ * rho_bar_k = sum_i (h_i + sum_j W_ij / 2) / sum_i a_ki.
+ * Parameters: pbit_net_param_count() floats in the order W1[128][16], b1,
+ * W2[128][128], b2, W3[128][144], b3, w4[128], b4 (row = output unit).
+ * Weights and stored activations are bf16, accumulation fp32 (matrix cores
+ * for the per-element layers).  All device buffers are caller-owned. */
+int32_t pbit_net_param_count(void);
+
+/* Device workspace for the activations of one forward/backward pair. */
+size_t pbit_net_workspace_bytes(int32_t sets, int32_t rows);
+
+/* Host: packs the sets of count instances.  Always writes *sets and *rows (a
+ * size query when x is NULL).  Otherwise fills, in host memory:
+ *   x        bf16 [rows][16]  set s occupies rows set_rows[s] .. (32-aligned),
+ *                             its first set_n[s] rows are its elements, the
+ *                             rest zero
+ *   ctx      bf16 [sets][16]
+ *   set_rows int32 [sets + 1]
+ *   set_n    int32 [sets]     (= n of the instance)
+ *   scale    double [sets]    lambda_q = t * scale
+ *   dest     int32 [sets]     member * 32 + k (index into a [count][32] array)
+ * Sets are ordered by member, then constraint.  Errors as pbit_plan. */
+pbit_status pbit_net_pack(const pbit_problem *probs, const pbit_params *params, int32_t count, int32_t *sets,
+                          int32_t *rows, uint16_t *x, uint16_t *ctx, int32_t *set_rows, int32_t *set_n,
+                          double *scale, int32_t *dest);
+
+/* bf16 copy of fp32 parameters (device).  Asynchronous on stream. */
+pbit_status pbit_net_cast(const float *w, uint16_t *w_bf16, pbit_stream stream);
+
+/* Forward pass of all sets: t[sets] (device fp32).  The packed arrays are the
+ * device copies of pbit_net_pack's output; w_bf16 and x 16-byte aligned; ws
+ * (256-byte aligned, pbit_net_workspace_bytes) keeps the activations for
+ * pbit_net_backward.  Asynchronous on stream. */
+pbit_status pbit_net_forward(const uint16_t *w_bf16, const uint16_t *x, const uint16_t *ctx,
+                             const int32_t *set_rows, const int32_t *set_n, int32_t sets, int32_t rows, void *ws,
+                             size_t ws_bytes, float *t, pbit_stream stream);
+
+/* Gradient (device fp32, pbit_net_param_count values) of the mean Huber loss
+ * (delta 1) of t - y over the sets, and the loss itself (device fp32 [1]),
+ * from the activations of the preceding pbit_net_forward on the same ws.
+ * Deterministic.  Asynchronous on stream. */
+pbit_status pbit_net_backward(const uint16_t *w_bf16, const uint16_t *x, const int32_t *set_rows,
+                              const int32_t *set_n, int32_t sets, int32_t rows, const float *t, const float *y,
+                              void *ws, size_t ws_bytes, float *grad, float *loss, pbit_stream stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step counts
+ * from 1) on fp32 master weights w with moments m, v; refreshes w_bf16. */
+pbit_status pbit_net_adam_step(float *w, float *m, float *v, const float *grad, uint16_t *w_bf16, int32_t step,
+                               float lr, pbit_stream stream);
+
+/* lambda_q[dest[s]] = round_half_away(t[s] * scale[s]) (float64, clamped to
+ * +-2^30), all device memory; feeds pbit_batch_set_lambdas. */
+pbit_status pbit_net_to_lambda(const float *t, const double *scale, const int32_t *dest, int32_t sets,
+                               int32_t *lambda_q, pbit_stream stream);
 
 /* Thread-local message describing the last failing call on this thread. */
 const char *pbit_last_error(void);

@@ -88,7 +88,29 @@ EXPORTS = {
     "pbit_batch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "pbit_destroy_batch": (ctypes.c_int, [ctypes.c_void_p]),
+    "pbit_batch_set_lambdas": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_batch_snapshot": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_net_param_count": (ctypes.c_int32, []),
+    "pbit_net_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "pbit_net_pack": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_net_cast": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_net_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_net_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "pbit_net_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p]),
+    "pbit_net_to_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
 }
+
+SNAPSHOT_BYTES = 160
+MAX_M = 32
 
 _LIB = None
 
@@ -352,6 +374,78 @@ class Instance:
             pass
 
 
+def pbit_batch_set_lambdas(batch: int, lambda_q, stream=None) -> None:
+    """lambda_q: int32 CUDA tensor [count][32]."""
+    _check(lib().pbit_batch_set_lambdas(batch, lambda_q.data_ptr(), _stream_handle(stream)))
+
+
+def pbit_batch_snapshot(batch: int, out, stream=None) -> None:
+    """out: uint8 CUDA tensor of count * 160 bytes."""
+    _check(lib().pbit_batch_snapshot(batch, out.data_ptr(), _stream_handle(stream)))
+
+
+def decode_snapshot(raw: np.ndarray, count: int) -> dict:
+    """Host view of pbit_batch_snapshot records."""
+    r = np.asarray(raw, dtype=np.uint8).reshape(count, SNAPSHOT_BYTES)
+    head = r[:, 8:32].copy().view(np.int32)
+    return {"best": r[:, :8].copy().view(np.int64).reshape(count),
+            "best_round": head[:, 0], "has_feasible": head[:, 1].astype(bool),
+            "rounds": head[:, 2], "feasible_last": head[:, 3],
+            "lambda_q": r[:, 32:].copy().view(np.int32).reshape(count, MAX_M)}
+
+
+# ---- learned starting multipliers -------------------------------------------
+
+def pbit_net_param_count() -> int:
+    return int(lib().pbit_net_param_count())
+
+
+def pbit_net_workspace_bytes(sets: int, rows: int) -> int:
+    return int(lib().pbit_net_workspace_bytes(int(sets), int(rows)))
+
+
+def pbit_net_pack(probs, pars) -> dict:
+    """Host arrays of the packed sets (x and ctx as uint16 bf16 bit patterns)."""
+    ms = _MarshalledSet(probs, pars)
+    sets, rows = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().pbit_net_pack(ms.problems, ms.params, ms.count, ctypes.byref(sets), ctypes.byref(rows),
+                               None, None, None, None, None, None))
+    S, R = int(sets.value), int(rows.value)
+    out = {"x": np.zeros((R, 16), np.uint16), "ctx": np.zeros((S, 16), np.uint16),
+           "set_rows": np.zeros(S + 1, np.int32), "set_n": np.zeros(S, np.int32),
+           "scale": np.zeros(S, np.float64), "dest": np.zeros(S, np.int32), "sets": S, "rows": R}
+    _check(lib().pbit_net_pack(ms.problems, ms.params, ms.count, ctypes.byref(sets), ctypes.byref(rows),
+                               out["x"].ctypes.data, out["ctx"].ctypes.data, out["set_rows"].ctypes.data,
+                               out["set_n"].ctypes.data, out["scale"].ctypes.data, out["dest"].ctypes.data))
+    return out
+
+
+def pbit_net_cast(w, w_bf16, stream=None) -> None:
+    _check(lib().pbit_net_cast(w.data_ptr(), w_bf16.data_ptr(), _stream_handle(stream)))
+
+
+def pbit_net_forward(w_bf16, x, ctx, set_rows, set_n, sets, rows, ws, t, stream=None) -> None:
+    _check(lib().pbit_net_forward(w_bf16.data_ptr(), x.data_ptr(), ctx.data_ptr(), set_rows.data_ptr(),
+                                  set_n.data_ptr(), int(sets), int(rows), ws.data_ptr(), ws.numel(),
+                                  t.data_ptr(), _stream_handle(stream)))
+
+
+def pbit_net_backward(w_bf16, x, set_rows, set_n, sets, rows, t, y, ws, grad, loss, stream=None) -> None:
+    _check(lib().pbit_net_backward(w_bf16.data_ptr(), x.data_ptr(), set_rows.data_ptr(), set_n.data_ptr(),
+                                   int(sets), int(rows), t.data_ptr(), y.data_ptr(), ws.data_ptr(), ws.numel(),
+                                   grad.data_ptr(), loss.data_ptr(), _stream_handle(stream)))
+
+
+def pbit_net_adam_step(w, m, v, grad, w_bf16, step: int, lr: float, stream=None) -> None:
+    _check(lib().pbit_net_adam_step(w.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(),
+                                    w_bf16.data_ptr(), int(step), float(lr), _stream_handle(stream)))
+
+
+def pbit_net_to_lambda(t, scale, dest, sets, lambda_q, stream=None) -> None:
+    _check(lib().pbit_net_to_lambda(t.data_ptr(), scale.data_ptr(), dest.data_ptr(), int(sets),
+                                    lambda_q.data_ptr(), _stream_handle(stream)))
+
+
 class Batch:
     """A set of instances run together (one persistent launch per round) in one
     torch-owned workspace.  members[i] is an Instance view of member i (its
@@ -380,6 +474,14 @@ class Batch:
 
     def rounds_left(self) -> np.ndarray:
         return pbit_batch_rounds_left(self.handle, len(self.members), self.stream)
+
+    def set_lambdas(self, lambda_q):
+        """lambda_q: int32 CUDA tensor [count][32]."""
+        pbit_batch_set_lambdas(self.handle, lambda_q, self.stream)
+
+    def snapshot(self, out):
+        """Queues the per-member records into out (uint8 CUDA tensor, count * 160 bytes)."""
+        pbit_batch_snapshot(self.handle, out, self.stream)
 
     def shape(self):
         """(work items, persistent workgroups, LDS bytes per workgroup)."""

@@ -23,6 +23,7 @@ SOURCES = [
     "round_kernels.hip",
     "sweep_quad.hip",
     "sweep_batch.hip",
+    "net_kernels.hip",
     "sweep_linear_a.hip",
     "sweep_linear_b.hip",
     "sweep_linear_c.hip",

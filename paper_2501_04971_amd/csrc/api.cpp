@@ -24,6 +24,7 @@
 
 #include "../../include/pbit.h"
 #include "pbit_types.h"
+#include "net_layout.h"
 
 namespace pbit {
 hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
@@ -47,6 +48,20 @@ const void *reset_counter_kernel();
 int reduce_threads();
 int batch_linear_m(int m);
 int batch_variant_code(int variant, int nb, int m);
+hipError_t launch_lambda_set_batch(const DevInstance *insts, int count, const int32_t *values, hipStream_t stream);
+hipError_t launch_batch_snapshot(const DevInstance *insts, int count, unsigned char *out, hipStream_t stream);
+hipError_t net_launch_forward(const uint16_t *w, const uint16_t *x, const uint16_t *ctx, const int *set_rows,
+                              const int *set_n, int S, int rows, uint16_t *H1, uint16_t *H2, uint16_t *Z,
+                              uint16_t *G1, float *t, hipStream_t st);
+hipError_t net_launch_backward(const uint16_t *w, const uint16_t *x, const int *set_rows, const int *set_n, int S,
+                               int rows, const uint16_t *H1, const uint16_t *H2, const uint16_t *Z,
+                               const uint16_t *G1, const float *t, const float *y, float *dP, float *partial,
+                               int groups, float *grad, float *loss, hipStream_t st);
+hipError_t net_launch_adam(float *wm, float *m, float *v, const float *g, uint16_t *wb, float lr, float b1,
+                           float b2, float eps, float bc1, float bc2, hipStream_t st);
+hipError_t net_launch_cast(const float *wm, uint16_t *wb, hipStream_t st);
+hipError_t net_launch_to_lambda(const float *t, const double *scale, const int *dest, int S, int *lam,
+                                hipStream_t st);
 }  // namespace pbit
 
 using namespace pbit;
@@ -790,6 +805,50 @@ hipError_t build_round_graph(pbit_batch *b)
     return hipSuccess;
 }
 
+
+// ---- lambda_0 set encoder: workspace layout and host features ----------------
+struct NetWs {
+    size_t H1, H2, Z, G1, dP, part, total;
+    int groups;
+};
+
+NetWs net_ws(int sets, int rows)
+{
+    NetWs w{};
+    size_t o = 0;
+    auto put = [&o](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    w.groups = std::min(sets, 64);
+    w.H1 = put((size_t)rows * kNetH * 2);
+    w.H2 = put((size_t)rows * kNetH * 2);
+    w.Z = put((size_t)sets * kNetZ * 2);
+    w.G1 = put((size_t)sets * kNetH * 2);
+    w.dP = put((size_t)sets * kNetH * 4);
+    w.part = put((size_t)w.groups * kNetPhiParams * 4);
+    w.total = o;
+    return w;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+uint16_t to_bf16(double v)
+{
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+pbit_status check_net_shape(int sets, int rows)
+{
+    if (sets < 1 || rows < 32 || rows % 32 != 0) return fail(PBIT_EINVAL, "sets >= 1 and rows a positive multiple of 32");
+    return PBIT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1143,6 +1202,205 @@ pbit_status pbit_destroy_batch(pbit_batch *b)
 {
     if (!b) return fail(PBIT_EINVAL, "null batch");
     delete b;
+    return PBIT_OK;
+}
+
+int32_t pbit_net_param_count(void) { return kNetParams; }
+
+size_t pbit_net_workspace_bytes(int32_t sets, int32_t rows)
+{
+    if (check_net_shape(sets, rows) != PBIT_OK) return 0;
+    return net_ws(sets, rows).total;
+}
+
+pbit_status pbit_net_pack(const pbit_problem *probs, const pbit_params *params, int32_t count, int32_t *sets_out,
+                          int32_t *rows_out, uint16_t *x, uint16_t *ctx, int32_t *set_rows, int32_t *set_n,
+                          double *scale, int32_t *dest)
+{
+    if (!probs || !params || count < 1 || !sets_out || !rows_out) return fail(PBIT_EINVAL, "null arguments");
+    int sets = 0, rows = 0;
+    std::vector<Plan> plans(count);
+    for (int i = 0; i < count; ++i) {
+        pbit_status st = make_plan(&probs[i], &params[i], plans[i]);
+        if (st != PBIT_OK) {
+            g_error = "member " + std::to_string(i) + ": " + g_error;
+            return st;
+        }
+        sets += probs[i].m;
+        rows += probs[i].m * ((probs[i].n + 31) / 32) * 32;
+    }
+    *sets_out = sets;
+    *rows_out = rows;
+    if (!x) return PBIT_OK;  // size query
+    if (!ctx || !set_rows || !set_n || !scale || !dest) return fail(PBIT_EINVAL, "null output array");
+    std::memset(x, 0, (size_t)rows * kNetF * 2);
+    std::memset(ctx, 0, (size_t)sets * kNetCtx * 2);
+    int s = 0, r = 0;
+    for (int i = 0; i < count; ++i) {
+        const pbit_problem &p = probs[i];
+        const Plan &P = plans[i];
+        const int n = p.n, m = p.m;
+        std::vector<double> h(n), rho(n), wsum(n, 0.0);
+        double s_f = 0.0;
+        if (p.kind == PBIT_QKP) {
+            for (int a = 0; a < n; ++a) {
+                for (int b = 0; b < n; ++b) {
+                    const double v = p.profit[(size_t)a * n + b];
+                    s_f = std::max(s_f, std::fabs(v));
+                    if (a != b) wsum[a] += v;
+                }
+                h[a] = p.profit[(size_t)a * n + a];
+            }
+        } else {
+            for (int a = 0; a < n; ++a) {
+                h[a] = p.profit[a];
+                s_f = std::max(s_f, std::fabs(h[a]));
+            }
+        }
+        s_f = std::max(s_f, 1.0);
+        double s_g = 1.0;
+        for (int k = 0; k < m; ++k) {
+            s_g = std::max(s_g, (double)p.capacity[k]);
+            for (int a = 0; a < n; ++a) s_g = std::max(s_g, (double)p.weight[(size_t)k * n + a]);
+        }
+        double half = 0.0;
+        for (int a = 0; a < n; ++a) {
+            rho[a] = h[a] + wsum[a];
+            half += h[a] + 0.5 * wsum[a];
+        }
+        std::vector<double> mean_ratio(n, 0.0);
+        for (int a = 0; a < n; ++a) {
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k)
+                acc += (double)p.weight[(size_t)k * n + a] / std::max((double)p.capacity[k], 1.0);
+            mean_ratio[a] = acc / m;
+        }
+        const double d = p.kind == PBIT_QKP ? (double)p.density_num / (double)p.density_den
+                                            : 2.0 / (P.n_ext + 1);
+        const double c6[6] = {std::log((double)P.n_ext) / 8.0, d, ((double)P.pq / 256.0) / P.n_ext,
+                              ((double)params[i].beta_num / params[i].beta_den) / 50.0, m / 32.0,
+                              p.kind == PBIT_QKP ? 0.0 : 1.0};
+        const int span = ((n + 31) / 32) * 32;
+        for (int k = 0; k < m; ++k, ++s) {
+            set_rows[s] = r;
+            set_n[s] = n;
+            dest[s] = i * kMaxM + k;
+            double asum = 0.0;
+            const double bk = std::max((double)p.capacity[k], 1.0);
+            for (int a = 0; a < n; ++a) {
+                const double ak = p.weight[(size_t)k * n + a];
+                asum += ak;
+                uint16_t *row = x + (size_t)(r + a) * kNetF;
+                row[0] = to_bf16(rho[a] / (s_f * n));
+                row[1] = to_bf16(n * (ak / bk));
+                row[2] = to_bf16(n * mean_ratio[a]);
+                row[3] = to_bf16(h[a] / s_f);
+            }
+            for (int c = 0; c < 6; ++c) ctx[(size_t)s * kNetCtx + c] = to_bf16(c6[c]);
+            const double rho_bar = half / (asum > 0 ? asum : 1.0);
+            scale[s] = 256.0 * rho_bar * s_g / s_f;
+            r += span;
+        }
+    }
+    set_rows[s] = r;
+    return PBIT_OK;
+}
+
+pbit_status pbit_net_cast(const float *w, uint16_t *w_bf16, pbit_stream stream)
+{
+    if (!w || !w_bf16) return fail(PBIT_EINVAL, "null buffer");
+    hipError_t e = net_launch_cast(w, w_bf16, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(PBIT_EDEVICE, std::string("net_cast: ") + hipGetErrorString(e));
+    return PBIT_OK;
+}
+
+pbit_status pbit_net_forward(const uint16_t *w_bf16, const uint16_t *x, const uint16_t *ctx,
+                             const int32_t *set_rows, const int32_t *set_n, int32_t sets, int32_t rows, void *ws,
+                             size_t ws_bytes, float *t, pbit_stream stream)
+{
+    pbit_status st = check_net_shape(sets, rows);
+    if (st != PBIT_OK) return st;
+    if (!w_bf16 || !x || !ctx || !set_rows || !set_n || !t) return fail(PBIT_EINVAL, "null buffer");
+    if (!aligned(w_bf16, 16) || !aligned(x, 16)) return fail(PBIT_EINVAL, "weights and inputs must be 16-byte aligned");
+    const NetWs L = net_ws(sets, rows);
+    if (!ws || !aligned(ws, 256) || ws_bytes < L.total) return fail(PBIT_EWORKSPACE, "net workspace too small");
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    hipError_t e = net_launch_forward(w_bf16, x, ctx, set_rows, set_n, sets, rows,
+                                      reinterpret_cast<uint16_t *>(b + L.H1), reinterpret_cast<uint16_t *>(b + L.H2),
+                                      reinterpret_cast<uint16_t *>(b + L.Z), reinterpret_cast<uint16_t *>(b + L.G1),
+                                      t, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(PBIT_EDEVICE, std::string("net_forward: ") + hipGetErrorString(e));
+    return PBIT_OK;
+}
+
+pbit_status pbit_net_backward(const uint16_t *w_bf16, const uint16_t *x, const int32_t *set_rows,
+                              const int32_t *set_n, int32_t sets, int32_t rows, const float *t, const float *y,
+                              void *ws, size_t ws_bytes, float *grad, float *loss, pbit_stream stream)
+{
+    pbit_status st = check_net_shape(sets, rows);
+    if (st != PBIT_OK) return st;
+    if (!w_bf16 || !x || !set_rows || !set_n || !t || !y || !grad || !loss) return fail(PBIT_EINVAL, "null buffer");
+    if (!aligned(w_bf16, 16) || !aligned(x, 16)) return fail(PBIT_EINVAL, "weights and inputs must be 16-byte aligned");
+    const NetWs L = net_ws(sets, rows);
+    if (!ws || !aligned(ws, 256) || ws_bytes < L.total) return fail(PBIT_EWORKSPACE, "net workspace too small");
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    hipError_t e = net_launch_backward(
+        w_bf16, x, set_rows, set_n, sets, rows, reinterpret_cast<const uint16_t *>(b + L.H1),
+        reinterpret_cast<const uint16_t *>(b + L.H2), reinterpret_cast<const uint16_t *>(b + L.Z),
+        reinterpret_cast<const uint16_t *>(b + L.G1), t, y, reinterpret_cast<float *>(b + L.dP),
+        reinterpret_cast<float *>(b + L.part), L.groups, grad, loss, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(PBIT_EDEVICE, std::string("net_backward: ") + hipGetErrorString(e));
+    return PBIT_OK;
+}
+
+pbit_status pbit_net_adam_step(float *w, float *m, float *v, const float *grad, uint16_t *w_bf16, int32_t step,
+                               float lr, pbit_stream stream)
+{
+    if (!w || !m || !v || !grad || !w_bf16) return fail(PBIT_EINVAL, "null buffer");
+    if (step < 1) return fail(PBIT_EINVAL, "step counts from 1");
+    const double b1 = 0.9, b2 = 0.999;
+    const float bc1 = (float)(1.0 - std::pow(b1, step)), bc2 = (float)(1.0 - std::pow(b2, step));
+    hipError_t e = net_launch_adam(w, m, v, grad, w_bf16, lr, (float)b1, (float)b2, 1e-8f, bc1, bc2,
+                                   reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(PBIT_EDEVICE, std::string("net_adam_step: ") + hipGetErrorString(e));
+    return PBIT_OK;
+}
+
+pbit_status pbit_net_to_lambda(const float *t, const double *scale, const int32_t *dest, int32_t sets,
+                               int32_t *lambda_q, pbit_stream stream)
+{
+    if (!t || !scale || !dest || !lambda_q || sets < 1) return fail(PBIT_EINVAL, "null buffer or sets < 1");
+    hipError_t e = net_launch_to_lambda(t, scale, dest, sets, lambda_q, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(PBIT_EDEVICE, std::string("net_to_lambda: ") + hipGetErrorString(e));
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_set_lambdas(pbit_batch *b, const int32_t *lambda_q, pbit_stream stream)
+{
+    pbit_status st = check_batch(b);
+    if (st != PBIT_OK) return st;
+    if (!lambda_q) return fail(PBIT_EINVAL, "null lambda array");
+    hipError_t e = launch_lambda_set_batch(b->d_insts, (int)b->members.size(), lambda_q,
+                                           reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return batch_error(b, e, "batch set_lambdas launch failed");
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_snapshot(pbit_batch *b, void *dev_out, pbit_stream stream)
+{
+    pbit_status st = check_batch(b);
+    if (st != PBIT_OK) return st;
+    if (!dev_out) return fail(PBIT_EINVAL, "null output");
+    hipError_t e = launch_batch_snapshot(b->d_insts, (int)b->members.size(), static_cast<unsigned char *>(dev_out),
+                                         reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return batch_error(b, e, "batch snapshot launch failed");
     return PBIT_OK;
 }
 

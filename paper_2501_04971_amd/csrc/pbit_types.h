@@ -12,6 +12,7 @@ constexpr int kMaxM = 32;                   // constraints per instance
 constexpr int kMaxQuadBlocks = 11;          // quadratic kernel: n_ext <= 352
 constexpr int kMaxWords = 64;               // linear kernel: n_ext <= 2048
 constexpr int kWave = 64;
+constexpr int kSnapshotBytes = 160;  // per-member record of batch snapshots
 
 // Everything a kernel needs about one instance; passed by value.
 struct DevInstance {

@@ -111,8 +111,8 @@ struct LambdaSet {
     int32_t v[kMaxM];
 };
 
-// mode 0: refresh constants only; 1: multiplier step from d.G; 2: set lambda_q from `set`.
-__device__ __forceinline__ void lambda_update_body(const DevInstance &d, int mode, const LambdaSet &set)
+// mode 0: refresh constants only; 1: multiplier step from d.G; 2: set lambda_q from `vals`.
+__device__ __forceinline__ void lambda_update_body(const DevInstance &d, int mode, const int32_t *vals)
 {
     __shared__ int32_t lq[kMaxM];
     const int tid = threadIdx.x;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void lambda_update_body(const DevInstance &d, int mod
         int64_t acc = d.lam_acc[tid];
         const int64_t cap = d.lq_max << 24;
         if (mode == 1) acc += round_scaled_div(d.eta_num * d.G[tid], d.lam_den);
-        if (mode == 2) acc = (int64_t)set.v[tid] * (1 << 24);
+        if (mode == 2) acc = (int64_t)vals[tid] * (1 << 24);
         acc = acc > cap ? cap : acc;
         acc = acc < -cap ? -cap : acc;
         const int32_t q = acc >= 0 ? (int32_t)((acc + (1 << 23)) >> 24)
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kReduceThreads) void round_reduce(const DevInstance
 
 __global__ __launch_bounds__(256) void lambda_update(const DevInstance d, int mode, LambdaSet set)
 {
-    lambda_update_body(d, mode, set);
+    lambda_update_body(d, mode, set.v);
 }
 
 // Batched forms: workgroup b serves instance b.  Members whose round budget is
@@ -162,10 +162,50 @@ __global__ __launch_bounds__(256) void lambda_update_batch(const DevInstance *in
 {
     const DevInstance d = insts[blockIdx.x];
     if (mode == 1 && d.rounds_left && d.rounds_left[0] <= 0) return;
-    LambdaSet none{};
-    lambda_update_body(d, mode, none);
+    lambda_update_body(d, mode, nullptr);
     __syncthreads();
     if (mode == 1 && d.rounds_left && threadIdx.x == 0) d.rounds_left[0] -= 1;
+}
+
+// Sets member b's lambda_q from values[b * kMaxM ..] (clamped to +-lq_max).
+__global__ __launch_bounds__(256) void lambda_set_batch(const DevInstance *insts, const int32_t *values)
+{
+    const DevInstance d = insts[blockIdx.x];
+    lambda_update_body(d, 2, values + (size_t)blockIdx.x * kMaxM);
+}
+
+// Per-member summary for host-side logs: best feasible profit and round, a
+// feasible flag, rounds done, and lambda_q (zero beyond m).
+__global__ __launch_bounds__(64) void batch_snapshot(const DevInstance *insts, unsigned char *out)
+{
+    const DevInstance d = insts[blockIdx.x];
+    unsigned char *rec = out + (size_t)blockIdx.x * kSnapshotBytes;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        *reinterpret_cast<int64_t *>(rec) = d.best[0];
+        int32_t *h = reinterpret_cast<int32_t *>(rec + 8);
+        h[0] = (int32_t)d.best[1];
+        h[1] = (int32_t)d.best[3];
+        h[2] = d.round_k[0];
+        h[3] = d.feas_count[0];
+        h[4] = 0;
+        h[5] = 0;
+    }
+    if (tid < kMaxM) reinterpret_cast<int32_t *>(rec + 32)[tid] = tid < d.m ? d.lam_q[tid] : 0;
+}
+
+hipError_t launch_lambda_set_batch(const DevInstance *insts, int count, const int32_t *values, hipStream_t stream)
+{
+    void *args[] = {&insts, &values};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&lambda_set_batch), dim3(count), dim3(256), args, 0,
+                           stream);
+}
+
+hipError_t launch_batch_snapshot(const DevInstance *insts, int count, unsigned char *out, hipStream_t stream)
+{
+    void *args[] = {&insts, &out};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&batch_snapshot), dim3(count), dim3(64), args, 0,
+                           stream);
 }
 
 __global__ void reset_counter(int *counter)
