@@ -10,6 +10,12 @@ timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
 
+Workloads: 0 QKP N=100 d=0.25 (64 replicas, 1000 sweeps), 1 MKP N=250 M=10
+(1024 replicas, 2000 sweeps), 2 QKP N=300 d=1 (4096 replicas, 5000 sweeps,
+the default), 3 the 512-instance mixed batch (256 QKP N in U{100..300},
+256 MKP N in {100,250,500} x M in {5,10,30}, 256 replicas each; one step =
+one graph replay of a round of every member).
+
 Prints one JSON line.  Only one GPU is supported.
 """
 from __future__ import annotations
@@ -21,38 +27,64 @@ import sys
 import time
 
 # Algorithmic integer ALU work of one spin update outside the field dot product
-# (which the int8 matrix cores do): a quarter of a Philox4x32-10 block
-# (10 rounds x 8 32-bit ops / 4), the field combination and beta-grid index
-# (8), the threshold compare (2) and the state/residual update (2 + 2M).
+# (which the int8 matrix cores do for the quadratic kernel): a quarter of a
+# Philox4x32-10 block (10 rounds x 8 32-bit ops / 4), the field combination
+# and beta-grid index (8), the threshold compare (2) and the state/residual
+# update (2 + 2M).
 ALU_OPS_RNG = 20
 ALU_OPS_FIXED = 12
 # 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz 32-bit lane-ops per second (the fp32
 # vector peak of 157.3 TFLOP/s counts an FMA as two operations).
 ALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
+SIMDS = 256 * 4
+# int8 matrix-core peak (dense) and LDS bandwidth (128 B/clk/CU)
+MFMA_I8_PEAK = 5.0e15
+LDS_PEAK = 256 * 128 * 2.4e9
+
+WORKLOAD_NAMES = {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10", 2: "QKP N=300 d=1.0",
+                  3: "mixed batch: 256 QKP + 256 MKP, 256 replicas each"}
 
 
 def alu_ops_per_update(m: int) -> int:
     return ALU_OPS_RNG + ALU_OPS_FIXED + 2 * m
 
 
-def cpu_baseline(prob, par, seconds_target: float = 10.0):
-    """The plain CPU oracle on a bounded sample of the same workload: the first
-    round of a few replicas with the full sweep count."""
+def quad_secondary(info, updates, seconds):
+    """int8 matrix-core ops and LDS bytes per update of the quadratic kernel:
+    every block of 32 visits runs 2 NB 32x32x32 int8 products per 64 replicas
+    (4096 NB ops per visit-of-64, i.e. 64 NB per update), and reads per visit
+    and wave the slab operands (32 x 32 NB bytes per 32 visits), the
+    threshold word (256 B) and the site record (32 B, broadcast)."""
+    nb = info.n_pad // 32
+    mfma_ops = 64 * nb * updates
+    lds_bytes = (32 * nb + 256 + 32) / 64 * updates
+    return {"mfma_int8": {"achieved": mfma_ops / seconds / 1e12, "peak": MFMA_I8_PEAK / 1e12,
+                          "unit": "TOP/s", "frac": mfma_ops / seconds / MFMA_I8_PEAK},
+            "lds": {"achieved": lds_bytes / seconds / 1e9, "peak": LDS_PEAK / 1e9, "unit": "GB/s",
+                    "frac": lds_bytes / seconds / LDS_PEAK}}
+
+
+def cpu_baseline(members, seconds_target: float = 10.0):
+    """The plain CPU oracle on a bounded sample of the same workload: round 0
+    of a few replicas (full sweep count) of the first member(s)."""
     from oracle import oracle as O
     threads = max(1, min(16, os.cpu_count() or 1))
-    prog = O.build_program(prob, par)
-    # calibrate on one replica per thread, then size the sample to ~seconds_target
-    t0 = time.perf_counter()
-    O.sa_round(prog, [0] * prog.m, 0, 0, threads, threads)
-    dt = time.perf_counter() - t0
-    reps = threads * max(1, min(8, int(seconds_target / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    O.sa_round(prog, [0] * prog.m, 0, threads, reps, threads)
-    dt = time.perf_counter() - t0
-    visits = reps * prog.n_ext * prog.T
-    return {"value": visits / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"round 0 of {reps} replicas x {prog.T} sweeps x {prog.n_ext} spins "
-                      f"({visits:.3g} updates, {dt:.1f} s)"}
+    t_all, visits_all, desc = 0.0, 0, []
+    for prob, par in members:
+        prog = O.build_program(prob, par)
+        t0 = time.perf_counter()
+        O.sa_round(prog, [0] * prog.m, 0, 0, threads, threads)
+        dt = time.perf_counter() - t0
+        budget = seconds_target / len(members)
+        reps = threads * max(1, min(8, int(budget / max(dt, 1e-3))))
+        t0 = time.perf_counter()
+        O.sa_round(prog, [0] * prog.m, 0, threads, reps, threads)
+        dt = time.perf_counter() - t0
+        t_all += dt
+        visits_all += reps * prog.n_ext * prog.T
+        desc.append(f"{reps} replicas x {prog.T} sweeps x {prog.n_ext} spins")
+    return {"value": visits_all / t_all, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"round 0 of: {'; '.join(desc)} ({visits_all:.3g} updates, {t_all:.1f} s)"}
 
 
 def main() -> int:
@@ -60,7 +92,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=2, choices=[0, 1, 2])
+    ap.add_argument("--workload", type=int, default=2, choices=[0, 1, 2, 3])
     ap.add_argument("--instance", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -68,7 +100,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the sampler shards by replicas and instances, see DESIGN.md)", file=sys.stderr)
+              "(the sampler would shard by replicas and instances across GPUs)", file=sys.stderr)
         return 2
 
     import torch
@@ -79,9 +111,6 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     B.lib()
-    prob, par, _ = G.workload(args.workload, args.instance)
-    inst = B.Instance(prob, par)
-    info = inst.info
     stream = torch.cuda.current_stream()
 
     if args.copy_mib > 0:
@@ -91,9 +120,32 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    batch = args.workload == 3
+    if batch:
+        members = [G.workload(3, i) for i in range(512)]
+        runner = B.Batch([p for p, _, _ in members], [q for _, q, _ in members],
+                         rounds=[1 << 30] * len(members))
+        infos = [m.info for m in runner.members]
+        updates_per_step = sum(q.replicas * i.n_ext * q.sweeps for (_, q, _), i in zip(members, infos))
+        ops_per_step = sum(alu_ops_per_update(p.m) * q.replicas * i.n_ext * q.sweeps
+                           for (p, q, _), i in zip(members, infos))
+
+        def step():
+            runner.run(1, use_graph=True)
+    else:
+        prob, par, _ = G.workload(args.workload, args.instance)
+        runner = B.Instance(prob, par)
+        info = runner.info
+        updates_per_step = par.replicas * info.n_ext * par.sweeps
+        ops_per_step = alu_ops_per_update(info.m) * updates_per_step
+
+        def step():
+            runner.sample_round()
+
     for _ in range(args.warmup):
-        inst.sample_round()
-        inst.update_lambda()
+        step()
+        if not batch:
+            runner.update_lambda()
     torch.cuda.synchronize()
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -105,22 +157,36 @@ def main() -> int:
     start.record(stream)
     for k in range(args.steps):
         ev[k][0].record(stream)
-        inst.sample_round()
+        step()
         ev[k][1].record(stream)
-        inst.update_lambda()
+        if not batch:
+            runner.update_lambda()
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = start.elapsed_time(end)
-    round_ms = [a.elapsed_time(b) for a, b in ev]
-    sweep_ms = sum(round_ms) / len(round_ms)
+    launch_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
 
-    updates_per_step = par.replicas * info.n_ext * par.sweeps
     value = updates_per_step * args.steps / (total_ms / 1e3)
-    ops = alu_ops_per_update(info.m) * updates_per_step
-    achieved = ops / (sweep_ms / 1e3)
-    best = inst.best_feasible()
-    inst.close()
+    achieved = ops_per_step / (launch_ms / 1e3)
+    if batch:
+        waves = sum((q.replicas + 255) // 256 * 4 for _, q, _ in members)
+        best = None
+        kernel = "sweep_batch + round epilogue + multiplier step (one graph replay)"
+        secondary = {}
+        cfg = {"workload": WORKLOAD_NAMES[3], "instances": len(members), "replicas_each": 256,
+               "sweeps_per_round": "QKP 1000, MKP 2000", "updates_per_step": updates_per_step,
+               "parallelism": "one GPU, persistent work queue over (instance, 256-replica tile)"}
+    else:
+        waves = (par.replicas + 63) // 64
+        best = runner.best_feasible()
+        kernel = "sweep_quad (annealing run + round epilogue)" if info.variant == 0 else \
+            "sweep_linear (annealing run + round epilogue)"
+        secondary = quad_secondary(info, updates_per_step, launch_ms / 1e3) if info.variant == 0 else {}
+        cfg = {"workload": WORKLOAD_NAMES[args.workload], "n_ext": info.n_ext, "constraints": info.m,
+               "replicas": par.replicas, "sweeps_per_round": par.sweeps,
+               "updates_per_step": updates_per_step, "parallelism": "one GPU, replicas across lanes"}
+    runner.close()
 
     out = {
         "metric": "p-bit spin updates/s",
@@ -135,29 +201,29 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "int32/int64 exact integer (int8 pair profits)",
         "data": "synthetic (seeded generators of the paper's instance families)",
-        "config": {
-            "workload": {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10",
-                         2: "QKP N=300 d=1.0"}[args.workload],
-            "n_ext": info.n_ext, "constraints": info.m, "replicas": par.replicas,
-            "sweeps_per_round": par.sweeps, "updates_per_step": updates_per_step,
-            "parallelism": "one GPU, replicas across lanes",
-        },
+        "config": cfg,
         "roofline": {
             "bound": "alu",
-            "kernel": "sweep (annealing run) + round epilogue, per launch",
+            "kernel": kernel,
             "achieved": achieved / 1e12,
             "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (32-bit integer)",
             "frac": achieved / ALU_PEAK_OPS,
             "traffic": None,
-            "ops_per_update": alu_ops_per_update(info.m),
-            "launch_ms": sweep_ms,
+            "ops_per_update": None if batch else alu_ops_per_update(info.m),
+            "launch_ms": launch_ms,
+            "waves": waves,
+            "frac_of_occupied_simds": achieved / (ALU_PEAK_OPS * min(1.0, waves / SIMDS)),
+            "secondary": secondary,
         },
         "wall_s": wall,
         "best_feasible_profit": None if best is None else best[0],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, par)
+        if batch:
+            out["cpu_baseline"] = cpu_baseline([members[0][:2], members[1][:2]])
+        else:
+            out["cpu_baseline"] = cpu_baseline([(prob, par)])
     print(json.dumps(out), flush=True)
     return 0
 

@@ -1,0 +1,351 @@
+"""Learned starting multipliers: data from the plain loop, training, evaluation.
+
+The plain method (Algorithm 1, lambda_0 = 0) is run on the GPU for many
+instances at once (pbit batch, graph replay); its multipliers settle to an
+instance-dependent lambda* (Fig. 3, Sec. IV).  A set encoder (library kernels
+pbit_net_*) is trained to predict t = lambda* / scale from instance features,
+and evaluated by the samples a run started from the prediction needs to reach
+the plain run's best feasible profit.  Everything numeric runs in the
+library; this module only schedules it and keeps the logs.
+
+    python -m paper_2501_04971_amd.learn gen   --out D --first 0 --count 2048
+    python -m paper_2501_04971_amd.learn train --data D --out W.npz
+    python -m paper_2501_04971_amd.learn eval  --weights W.npz --first 1000000 --count 256
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from fractions import Fraction
+
+import numpy as np
+
+from . import binding as B
+from . import generators as G
+
+# Table 1 settings of the paper's QKP experiments (beta_max 10, eta 20,
+# P = 2 d N, 1000 MCS per run); replicas per round and rounds per run are this
+# implementation's choice.
+QKP_PARAMS = dict(replicas=256, sweeps=1000, beta=Fraction(10), eta=Fraction(20), alpha=Fraction(2))
+EVAL_SEED_BASE = 1_000_000
+
+
+def learn_instance(index: int):
+    """Instance `index` of the learned-start workload: QKP with N=300, d=1 for
+    even indices (the throughput workload's generator), QKP with N in U{100..300},
+    d in {.25,.5,.75,1} (the mixed batch's QKP generator) for odd ones."""
+    if index % 2 == 0:
+        prob = G.family2(index)
+    else:
+        prob = G.family3(2 * index)  # even family-3 indices are QKP
+    par = G.Params(instance_id=index & 0xFFFFFFFF, **QKP_PARAMS)
+    return prob, par
+
+
+def run_loop(probs, pars, rounds: int, lambda0=None, blocks: int = 0, log=print):
+    """Runs `rounds` rounds of the plain loop for every instance (from lambda0,
+    int32 [count][32] host array, or 0) and returns per-round host logs:
+      lam  [rounds+1, count, 32]  multipliers in force at round k (k = rounds: final)
+      best [rounds, count]        best feasible profit after round k (INT64_MIN if none)
+      has  [rounds, count]        any feasible sample yet"""
+    import torch
+    count = len(probs)
+    batch = B.Batch(probs, pars, rounds=[rounds] * count, blocks=blocks)
+    if lambda0 is not None:
+        batch.set_lambdas(torch.from_numpy(np.ascontiguousarray(lambda0, dtype=np.int32)).cuda())
+    snap = torch.empty((rounds + 1, count * B.SNAPSHOT_BYTES), dtype=torch.uint8, device="cuda")
+    batch.snapshot(snap[0])
+    t0 = time.perf_counter()
+    for k in range(rounds):
+        batch.run(1, use_graph=True)
+        batch.snapshot(snap[k + 1])
+        if (k + 1) % 50 == 0:
+            torch.cuda.synchronize()
+            log(f"  round {k + 1}/{rounds}  {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    raw = snap.cpu().numpy()
+    batch.close()
+    recs = [B.decode_snapshot(raw[k], count) for k in range(rounds + 1)]
+    lam = np.stack([r["lambda_q"] for r in recs])
+    best = np.stack([r["best"] for r in recs[1:]])
+    has = np.stack([r["has_feasible"] for r in recs[1:]])
+    return {"lam": lam, "best": best, "has": has, "seconds": time.perf_counter() - t0}
+
+
+def settled_lambda(lam: np.ndarray, m: np.ndarray, tol: float = 0.01):
+    """lambda* = mean of the multipliers over the last quarter of the rounds;
+    settled when the mean over the third quarter differs from it by less than
+    tol relative (per constraint, all constraints of the instance)."""
+    K = lam.shape[0] - 1
+    q = max(1, K // 4)
+    last = lam[K - q + 1:K + 1].astype(np.float64).mean(axis=0)
+    prev = lam[K - 2 * q + 1:K - q + 1].astype(np.float64).mean(axis=0)
+    rel = np.abs(last - prev) / np.maximum(np.abs(last), 1.0)
+    ok = np.array([(rel[i, :m[i]] < tol).all() for i in range(lam.shape[1])])
+    return last, ok
+
+
+def samples_to_target(best: np.ndarray, has: np.ndarray, target: np.ndarray, replicas: int):
+    """Samples (rounds x replicas) until the best feasible profit reaches
+    target, per instance; -1 if never."""
+    hit = has & (best >= target[None, :])
+    out = np.full(best.shape[1], -1, dtype=np.int64)
+    for i in range(best.shape[1]):
+        k = np.nonzero(hit[:, i])[0]
+        if k.size:
+            out[i] = (int(k[0]) + 1) * replicas
+    return out
+
+
+def cmd_gen(args):
+    os.makedirs(args.out, exist_ok=True)
+    idx = list(range(args.first, args.first + args.count))
+    ms = [learn_instance(i) for i in idx]
+    print(f"gen: {len(ms)} instances, {args.rounds} rounds", flush=True)
+    res = run_loop([p for p, _ in ms], [q for _, q in ms], args.rounds)
+    m = np.array([p.m for p, _ in ms])
+    lstar, ok = settled_lambda(res["lam"], m)
+    path = os.path.join(args.out, f"plain_{args.first}_{args.count}.npz")
+    np.savez_compressed(path, index=np.array(idx), lam_star=lstar, settled=ok, m=m,
+                        best=res["best"][-1], has=res["has"][-1], lam=res["lam"][:, :, :1].astype(np.int32))
+    print(json.dumps({"out": path, "settled": int(ok.sum()), "count": len(ms), "seconds": res["seconds"]}),
+          flush=True)
+
+
+def load_data(paths):
+    idx, lstar, ok = [], [], []
+    for p in paths:
+        z = np.load(p)
+        idx.append(z["index"])
+        lstar.append(z["lam_star"])
+        ok.append(z["settled"])
+    return np.concatenate(idx), np.concatenate(lstar), np.concatenate(ok)
+
+
+class Trainer:
+    """fp32 master weights + Adam moments on the device; minibatches of packed
+    instance sets."""
+
+    def __init__(self, seed: int = 0, weights=None):
+        import torch
+        n = B.pbit_net_param_count()
+        if weights is None:
+            weights = init_weights(seed)
+        self.w = torch.from_numpy(np.asarray(weights, np.float32).copy()).cuda()
+        self.m = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.v = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.g = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.wb = torch.empty(n, dtype=torch.int16, device="cuda")
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        self.step = 0
+        B.pbit_net_cast(self.w, self.wb)
+
+    @staticmethod
+    def upload(pk):
+        import torch
+        d = {k: torch.from_numpy(np.ascontiguousarray(pk[k])).cuda()
+             for k in ("set_rows", "set_n", "scale", "dest")}
+        d["x"] = torch.from_numpy(pk["x"].view(np.int16)).cuda()
+        d["ctx"] = torch.from_numpy(pk["ctx"].view(np.int16)).cuda()
+        d["sets"], d["rows"] = pk["sets"], pk["rows"]
+        d["ws"] = torch.empty(B.pbit_net_workspace_bytes(pk["sets"], pk["rows"]), dtype=torch.uint8,
+                              device="cuda")
+        d["t"] = torch.empty(pk["sets"], dtype=torch.float32, device="cuda")
+        return d
+
+    def forward(self, d):
+        B.pbit_net_forward(self.wb, d["x"], d["ctx"], d["set_rows"], d["set_n"], d["sets"], d["rows"],
+                           d["ws"], d["t"])
+        return d["t"]
+
+    def train_step(self, d, y, lr):
+        self.forward(d)
+        B.pbit_net_backward(self.wb, d["x"], d["set_rows"], d["set_n"], d["sets"], d["rows"], d["t"], y,
+                            d["ws"], self.g, self.loss)
+        self.step += 1
+        B.pbit_net_adam_step(self.w, self.m, self.v, self.g, self.wb, self.step, lr)
+
+    def predict_lambda(self, d, count: int):
+        """int32 CUDA tensor [count][32] of predicted lambda_q."""
+        import torch
+        self.forward(d)
+        lam = torch.zeros(count * 32, dtype=torch.int32, device="cuda")
+        B.pbit_net_to_lambda(d["t"], d["scale"], d["dest"], d["sets"], lam)
+        return lam
+
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "lambda0_qkp.npz")
+
+
+def predict_lambda0(probs, pars, weights: str = DEFAULT_WEIGHTS):
+    """Predicted starting multipliers, int32 CUDA tensor [count][32], for
+    pbit_batch_set_lambdas (members in the given order)."""
+    z = np.load(weights)
+    T = Trainer(weights=z["weights"])
+    d = Trainer.upload(B.pbit_net_pack(probs, pars))
+    return T.predict_lambda(d, len(probs))
+
+
+def init_weights(seed: int) -> np.ndarray:
+    """He-uniform weights, zero biases, in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    shapes = [(128, 16), (128,), (128, 128), (128,), (128, 144), (128,), (128,), (1,)]
+    parts = []
+    for s in shapes:
+        if len(s) == 2:
+            lim = np.sqrt(6.0 / s[1])
+            parts.append(rng.uniform(-lim, lim, size=s).reshape(-1))
+        elif s == (128,) and len(parts) == 6:
+            parts.append(rng.uniform(-np.sqrt(6.0 / 128), np.sqrt(6.0 / 128), size=s))
+        else:
+            parts.append(np.zeros(s))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def cmd_train(args):
+    import torch
+    files = sorted(os.path.join(args.data, f) for f in os.listdir(args.data) if f.startswith("plain_"))
+    idx, lstar, ok = load_data(files)
+    keep = np.nonzero(ok)[0]
+    print(f"train: {ok.sum()} settled of {len(ok)}", flush=True)
+    idx, lstar = idx[keep], lstar[keep]
+    ms = [learn_instance(int(i)) for i in idx]
+    rng = np.random.default_rng(args.seed)
+    order = rng.permutation(len(ms))
+    nval = max(1, len(ms) // 10)
+    val, tr = order[:nval], order[nval:]
+    mb = args.minibatch
+
+    def make(sel):
+        pk = B.pbit_net_pack([ms[i][0] for i in sel], [ms[i][1] for i in sel])
+        y = np.zeros(pk["sets"], np.float32)
+        for s in range(pk["sets"]):
+            mem, k = divmod(int(pk["dest"][s]), 32)
+            y[s] = lstar[sel[mem], k] / pk["scale"][s]
+        d = Trainer.upload(pk)
+        d["y"] = torch.from_numpy(y).cuda()
+        return d
+
+    batches = [make(tr[i:i + mb]) for i in range(0, len(tr), mb)]
+    vbatch = make(val)
+    T = Trainer(args.seed)
+    hist = []
+    for ep in range(args.epochs):
+        lr = args.lr * (0.5 * (1 + np.cos(np.pi * ep / args.epochs)))
+        tot = 0.0
+        for j in rng.permutation(len(batches)):
+            T.train_step(batches[j], batches[j]["y"], lr)
+            tot += float(T.loss.cpu()[0])
+        T.forward(vbatch)
+        B.pbit_net_backward(T.wb, vbatch["x"], vbatch["set_rows"], vbatch["set_n"], vbatch["sets"],
+                            vbatch["rows"], vbatch["t"], vbatch["y"], vbatch["ws"], T.g, T.loss)
+        vl = float(T.loss.cpu()[0])
+        hist.append((tot / len(batches), vl))
+        if ep % max(1, args.epochs // 20) == 0 or ep == args.epochs - 1:
+            print(f"epoch {ep}: train {tot / len(batches):.5f} val {vl:.5f}", flush=True)
+    ytr = np.concatenate([b["y"].cpu().numpy() for b in batches])
+    np.savez(args.out, weights=T.w.cpu().numpy(), history=np.array(hist),
+             train_index=idx[tr], val_index=idx[val], y_median=np.median(ytr))
+    print(json.dumps({"out": args.out, "train": len(tr), "val": len(val), "final_val_loss": hist[-1][1]}),
+          flush=True)
+
+
+def compare(plain, other, K: int, R: int):
+    """Samples-to-target of `other` against the plain run, both truncated to
+    their first K rounds (runs are deterministic, so a truncated log is the log
+    of a shorter run).  Target: the plain run's best feasible profit after K
+    rounds, less 0.1 %."""
+    pb, ph = plain["best"][:K], plain["has"][:K]
+    ob, oh = other["best"][:K], other["has"][:K]
+    ok = ph[-1]
+    target = np.where(ok, pb[-1] - np.floor(np.abs(pb[-1]) * 0.001), 0)
+    sp = samples_to_target(pb, ph, target, R)
+    so = samples_to_target(ob, oh, target, R)
+    # fallback: no feasible sample by a quarter of the rounds -> the plain
+    # run's samples are added to its own budget
+    fb = ~oh[max(1, K // 4) - 1]
+    so_fb = np.where(fb, np.where(so > 0, so, K * R) + sp, so)
+    both = ok & (sp > 0) & (so_fb > 0)
+    ratio = sp[both] / so_fb[both]
+    return {
+        "rounds": K, "plain_feasible": int(ok.sum()), "reached_target": int((so > 0)[ok].sum()),
+        "fallbacks": int(fb[ok].sum()),
+        "median_samples_plain": float(np.median(sp[both])) if both.any() else None,
+        "median_samples_other": float(np.median(so_fb[both])) if both.any() else None,
+        "geomean_ratio_plain_over_other": float(np.exp(np.mean(np.log(ratio)))) if both.any() else None,
+        "median_ratio_plain_over_other": float(np.median(ratio)) if both.any() else None,
+        "fraction_fewer_samples": float((so_fb[both] < sp[both]).mean()) if both.any() else None,
+        "final_best_ratio_mean": float(np.mean(np.where(oh[-1], ob[-1], 0)[ok] / np.maximum(pb[-1][ok], 1))),
+    }
+
+
+def cmd_eval(args):
+    z = np.load(args.weights)
+    T = Trainer(weights=z["weights"])
+    idx = list(range(args.first, args.first + args.count))
+    ms = [learn_instance(i) for i in idx]
+    probs, pars = [p for p, _ in ms], [q for _, q in ms]
+    pk = B.pbit_net_pack(probs, pars)
+    d = Trainer.upload(pk)
+    lam0 = T.predict_lambda(d, len(ms)).cpu().numpy().reshape(len(ms), 32)
+    # scale-only start: the training targets' median t for every instance
+    c = float(z["y_median"])
+    lam_c = np.zeros_like(lam0)
+    for s in range(pk["sets"]):
+        v = c * pk["scale"][s]
+        lam_c.reshape(-1)[pk["dest"][s]] = int(np.floor(abs(v) + 0.5)) * (1 if v >= 0 else -1)
+    print(f"eval: {len(ms)} held-out instances, {args.rounds} rounds per form", flush=True)
+    plain = run_loop(probs, pars, args.rounds)
+    learned = run_loop(probs, pars, args.rounds, lambda0=lam0)
+    const = run_loop(probs, pars, args.rounds, lambda0=lam_c)
+    R = pars[0].replicas
+    lam_plain_final = plain["lam"][-1][:, 0].astype(np.float64)
+    res = {"instances": len(ms), "replicas": R, "sweeps": pars[0].sweeps,
+           "lambda0_rel_err_median": {
+               "learned": float(np.median(np.abs(lam0[:, 0] - lam_plain_final) / np.maximum(np.abs(lam_plain_final), 1))),
+               "scale_only": float(np.median(np.abs(lam_c[:, 0] - lam_plain_final) / np.maximum(np.abs(lam_plain_final), 1)))},
+           "by_rounds": {}}
+    for K in sorted({k for k in (100, 200, args.rounds) if k <= args.rounds}):
+        res["by_rounds"][str(K)] = {"learned": compare(plain, learned, K, R),
+                                    "scale_only": compare(plain, const, K, R)}
+    res["seconds"] = plain["seconds"] + learned["seconds"] + const["seconds"]
+    if args.out:
+        np.savez_compressed(args.out, index=np.array(idx), lam0=lam0[:, 0], lam_const=lam_c[:, 0],
+                            plain_best=plain["best"], learned_best=learned["best"], const_best=const["best"],
+                            plain_has=plain["has"], learned_has=learned["has"], const_has=const["has"],
+                            plain_lam=plain["lam"][:, :, 0], learned_lam=learned["lam"][:, :, 0])
+    print(json.dumps(res), flush=True)
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("gen")
+    g.add_argument("--out", required=True)
+    g.add_argument("--first", type=int, default=0)
+    g.add_argument("--count", type=int, default=512)
+    g.add_argument("--rounds", type=int, default=300)
+    t = sub.add_parser("train")
+    t.add_argument("--data", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--epochs", type=int, default=200)
+    t.add_argument("--minibatch", type=int, default=64)
+    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--seed", type=int, default=0)
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--first", type=int, default=EVAL_SEED_BASE)
+    e.add_argument("--count", type=int, default=256)
+    e.add_argument("--rounds", type=int, default=100)
+    e.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    {"gen": cmd_gen, "train": cmd_train, "eval": cmd_eval}[args.cmd](args)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,46 @@
+"""Autotuner: shape keys, candidate sets and the JSON cache on the host; on the
+GPU, tuning picks a layout whose results are the oracle's."""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2501_04971_amd import autotune as A
+from paper_2501_04971_amd import binding as B
+from paper_2501_04971_amd import generators as G
+
+
+def test_keys_candidates_and_cache(tmp_path):
+    q = G.qkp(90, Fraction(1, 2), G.rng_for(980, 0))
+    m = G.mkp(120, 7, G.rng_for(980, 1))
+    par = G.Params(replicas=300, sweeps=10)
+    iq, im = B.pbit_plan(q, par), B.pbit_plan(m, par)
+    assert iq.n_pad == (iq.n_ext + 31) // 32 * 32
+    assert A.shape_key(iq, 300) == f"v0-n{iq.n_pad}-m1-r512"
+    assert A.shape_key(im, 300).startswith("v1-n") and A.shape_key(im, 300).endswith("-m7-r512")
+    assert A.candidates(iq) == [(1, -1), (4, -1)]
+    assert len(A.candidates(im)) == 8
+    path = str(tmp_path / "t.json")
+    assert A.load_cache(path) == {}
+    A.save_cache({"k": {"waves_per_block": 4, "lds_resident": -1}}, path)
+    assert A.load_cache(path)["k"]["waves_per_block"] == 4
+
+
+@pytest.mark.gpu
+def test_tuned_layout_is_used_and_exact(need_gpu, tmp_path):
+    from oracle import oracle as O
+    path = str(tmp_path / "tiling.json")
+    prob = G.mkp(100, 5, G.rng_for(981, 0))
+    par = G.Params(replicas=200, sweeps=20, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
+    entry = A.tune_instance(prob, par, probe_sweeps=10, reps=1, path=path)
+    assert len(entry["probe_ms"]) == 8
+    inst = B.Instance(prob, par)
+    got = A.apply(inst, prob, par, tune_missing=False, path=path)
+    assert got == entry
+    inst.sample_round()
+    out = inst.round_outputs()
+    inst.close()
+    ref = O.saim(prob, par, 1, nthreads=8)["rounds"][0]
+    assert (B.unpack_bits(out["x_bits"], ref["x"].shape[1]) == ref["x"]).all()
+    assert (out["g"] == ref["g"]).all()

@@ -1,0 +1,42 @@
+"""The learned start end to end on the GPU: training with the library's own
+kernels lowers the loss, and the shipped network (trained on multipliers the
+plain loop settled to) reaches the plain loop's best feasible profit in fewer
+samples on held-out instances."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2501_04971_amd import binding as B
+from paper_2501_04971_amd import learn as L
+
+pytestmark = pytest.mark.gpu
+
+
+def test_training_lowers_the_loss(need_gpu):
+    import torch
+    ms = [L.learn_instance(50_000 + i) for i in range(16)]
+    pk = B.pbit_net_pack([p for p, _ in ms], [q for _, q in ms])
+    d = L.Trainer.upload(pk)
+    y = torch.from_numpy(np.random.default_rng(0).uniform(0.8, 1.2, pk["sets"]).astype(np.float32)).cuda()
+    T = L.Trainer(seed=3)
+    losses = []
+    for _ in range(300):
+        T.train_step(d, y, 3e-3)
+        losses.append(float(T.loss.cpu()[0]))
+    assert losses[-1] < 0.1 * losses[0], (losses[0], losses[-1])
+
+
+@pytest.mark.skipif(not os.path.exists(L.DEFAULT_WEIGHTS), reason="no trained weights shipped")
+def test_learned_start_needs_fewer_samples(need_gpu):
+    count, K = 32, 100
+    ms = [L.learn_instance(L.EVAL_SEED_BASE + 7000 + i) for i in range(count)]
+    probs, pars = [p for p, _ in ms], [q for _, q in ms]
+    lam0 = L.predict_lambda0(probs, pars).cpu().numpy().reshape(count, 32)
+    plain = L.run_loop(probs, pars, K)
+    learned = L.run_loop(probs, pars, K, lambda0=lam0)
+    res = L.compare(plain, learned, K, pars[0].replicas)
+    print(res, flush=True)
+    assert res["plain_feasible"] >= count // 2
+    assert res["reached_target"] >= 0.9 * res["plain_feasible"]
+    assert res["geomean_ratio_plain_over_other"] > 1.5
