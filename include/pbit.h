@@ -184,11 +184,15 @@ pbit_status pbit_instance_info(const pbit_instance *inst, pbit_plan_info *out);
  * kernel 1..4; 0 = the default for the replica count).  lds_resident selects,
  * for the linear kernel, whether the per-site field constants and coefficient
  * rows are staged in LDS (1), read from global memory (0), or staged whenever
- * they fit (-1, the default); ignored by the quadratic kernel.  Every layout
- * gives bit-identical results; only the speed differs.  Host only, takes
- * effect at the next pbit_sample_round.  PBIT_ERANGE if lds_resident = 1 does
- * not fit the 160 KB of LDS at this tiling. */
-pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_t lds_resident);
+ * they fit (-1, the default); ignored by the quadratic kernel.  split selects,
+ * for the quadratic kernel, workgroups of one visiting wave plus three waves
+ * that precompute its random draws, thresholds and J slabs (1), plain
+ * workgroups (0), or the split form whenever the replicas leave CUs idle (-1,
+ * the default); 1 is rejected for the linear kernel.  Every layout gives
+ * bit-identical results; only the speed differs.  Host only, takes effect at
+ * the next pbit_sample_round.  PBIT_ERANGE if lds_resident = 1 does not fit
+ * the 160 KB of LDS at this tiling. */
+pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_t lds_resident, int32_t split);
 
 /* ---- Batched execution --------------------------------------------------
  * A batch runs many independent instances, of either kind and of uneven

@@ -5,8 +5,9 @@ lane, the same Philox counters and the same visit order), so the choice is
 purely a speed question, answered by measurement:
 
 * single instances: waves of 64 replicas per workgroup (quadratic kernel 1 or
-  4; linear kernel 1..4) and, for the linear kernel, whether the per-site
-  constants are staged in LDS or read from global memory;
+  4; linear kernel 1..4), for the linear kernel whether the per-site
+  constants are staged in LDS or read from global memory, and for the
+  quadratic kernel the producer/consumer split;
 * batches: the persistent grid size.
 
 A probe run with a reduced sweep count times each candidate (the cost of a
@@ -47,9 +48,10 @@ def shape_key(info, replicas: int) -> str:
 
 
 def candidates(info):
+    """(waves per workgroup, LDS residency, split) triples."""
     if info.variant == 0:
-        return [(1, -1), (4, -1)]
-    return [(w, r) for w in (1, 2, 3, 4) for r in (0, 1)]
+        return [(1, -1, 0), (4, -1, 0), (4, -1, 1)]
+    return [(w, r, 0) for w in (1, 2, 3, 4) for r in (0, 1)]
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -92,16 +94,17 @@ def tune_instance(prob, par, probe_sweeps: int = 40, reps: int = 3, path: str | 
     inst = B.Instance(prob, probe)
     key = shape_key(inst.info, par.replicas)
     timings = {}
-    for wpb, res in candidates(inst.info):
+    for wpb, res, split in candidates(inst.info):
         try:
-            inst.set_tiling(wpb, res)
+            inst.set_tiling(wpb, res, split)
         except B.PbitError:
             continue  # does not fit this shape
-        timings[f"{wpb},{res}"] = _time_rounds(inst.sample_round, reps)
+        timings[f"{wpb},{res},{split}"] = _time_rounds(inst.sample_round, reps)
     inst.close()
     best = min(timings, key=timings.get)
-    entry = {"waves_per_block": int(best.split(",")[0]), "lds_resident": int(best.split(",")[1]),
-             "probe_ms": timings, "probe_sweeps": probe.sweeps}
+    w, r, sp = (int(v) for v in best.split(","))
+    entry = {"waves_per_block": w, "lds_resident": r, "split": sp, "probe_ms": timings,
+             "probe_sweeps": probe.sweeps}
     cache = load_cache(path)
     cache[key] = entry
     save_cache(cache, path)
@@ -116,7 +119,7 @@ def apply(inst, prob, par, tune_missing: bool = True, path: str | None = None) -
     if entry is None and tune_missing:
         entry = tune_instance(prob, par, path=path)
     if entry is not None:
-        inst.set_tiling(entry["waves_per_block"], entry["lds_resident"])
+        inst.set_tiling(entry["waves_per_block"], entry["lds_resident"], entry.get("split", -1))
     return entry
 
 

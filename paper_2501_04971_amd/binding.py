@@ -74,7 +74,7 @@ EXPORTS = {
     "pbit_last_error": (ctypes.c_char_p, []),
     "pbit_theta_table": (ctypes.c_int, [ctypes.c_void_p]),
     "pbit_instance_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
-    "pbit_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "pbit_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "pbit_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "pbit_create_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -241,8 +241,8 @@ def pbit_instance_info(inst: int) -> pbit_plan_info:
     return info
 
 
-def pbit_set_tiling(inst: int, waves_per_block: int, lds_resident: int = -1) -> None:
-    _check(lib().pbit_set_tiling(inst, int(waves_per_block), int(lds_resident)))
+def pbit_set_tiling(inst: int, waves_per_block: int, lds_resident: int = -1, split: int = -1) -> None:
+    _check(lib().pbit_set_tiling(inst, int(waves_per_block), int(lds_resident), int(split)))
 
 
 class _MarshalledSet:
@@ -323,8 +323,8 @@ class Instance:
             self.info = pbit_instance_info(_member)
         self.outbuf = torch.empty(int(self.info.out_bytes), dtype=torch.uint8, device="cuda")
 
-    def set_tiling(self, waves_per_block: int, lds_resident: int = -1):
-        pbit_set_tiling(self.handle, waves_per_block, lds_resident)
+    def set_tiling(self, waves_per_block: int, lds_resident: int = -1, split: int = -1):
+        pbit_set_tiling(self.handle, waves_per_block, lds_resident, split)
 
     def sample_round(self):
         pbit_sample_round(self.handle, self.stream)

@@ -22,6 +22,7 @@ SOURCES = [
     "api.cpp",
     "round_kernels.hip",
     "sweep_quad.hip",
+    "sweep_quad_pc.hip",
     "sweep_batch.hip",
     "net_kernels.hip",
     "sweep_linear_a.hip",

@@ -28,6 +28,7 @@
 
 namespace pbit {
 hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
+hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, hipStream_t stream);
 hipError_t launch_sweep_linear_a(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
 hipError_t launch_sweep_linear_b(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
 hipError_t launch_sweep_linear_c(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
@@ -521,6 +522,8 @@ struct pbit_instance {
     int device = 0;
     int wpb = 1;
     int resident = -1;    // linear kernels: 1 LDS-resident constants, 0 global, -1 whichever fits
+    int split = -1;       // quadratic kernel: 1 producer/consumer workgroups, 0 not, -1 when CUs would idle
+    int cus = 256;
     bool broken = false;
     bool member = false;  // owned by a batch
 };
@@ -588,6 +591,7 @@ pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *
         delete inst;
         return fail(PBIT_EDEVICE, std::string("device query failed: ") + hipGetErrorString(e));
     }
+    inst->cus = prop.multiProcessorCount;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
         delete inst;
         return fail(PBIT_EDEVICE, std::string("libpbit is built for gfx950, device is ") + prop.gcnArchName);
@@ -895,9 +899,11 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
     const DevInstance &d = inst->dev;
     hipError_t e;
     switch (inst->plan.variant) {
-        case kQuad:
-            e = launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
+        case kQuad: {
+            const bool pc = inst->split == 1 || (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus);
+            e = pc ? launch_sweep_quad_pc(d, inst->plan.nb, s) : launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
             break;
+        }
         default: {
             const bool wide = inst->plan.variant == kLinearWide;
             const bool res = inst->resident == 1 ||
@@ -1015,7 +1021,7 @@ pbit_status pbit_instance_info(const pbit_instance *inst, pbit_plan_info *out)
     return PBIT_OK;
 }
 
-pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_t lds_resident)
+pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_t lds_resident, int32_t split)
 {
     pbit_status st = check_live(inst);
     if (st != PBIT_OK) return st;
@@ -1024,10 +1030,12 @@ pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_
     const bool ok = quad ? (wpb == 1 || wpb == 4) : (wpb >= 1 && wpb <= 4);
     if (!ok) return fail(PBIT_EINVAL, "waves per block must be 1 or 4 (quadratic) or 1..4 (linear)");
     if (lds_resident < -1 || lds_resident > 1) return fail(PBIT_EINVAL, "lds_resident must be -1, 0 or 1");
+    if (split < -1 || split > 1 || (split == 1 && !quad)) return fail(PBIT_EINVAL, "split must be -1, 0 or 1 (1: quadratic only)");
     if (!quad && lds_resident == 1 && resident_bytes(inst->plan, wpb) > kMaxLds)
         return fail(PBIT_ERANGE, "site constants do not fit LDS at this tiling");
     inst->wpb = wpb;
     inst->resident = quad ? -1 : lds_resident;
+    inst->split = quad ? split : 0;
     return PBIT_OK;
 }
 

@@ -73,6 +73,27 @@ __host__ __device__ __forceinline__ int32_t theta_index(int64_t Z, int32_t B, in
     return q;
 }
 
+// hi = floor((Z*B + 2^(S'-1)) / 2^32) for a field carried as Z' = 2^u Z (the
+// first step of theta_index, exact for |Z| < 2^62, 0 <= B < 2^31).
+__host__ __device__ __forceinline__ int64_t field_hi(int64_t Z, int32_t B, int64_t irnd)
+{
+    const uint64_t lo = (uint64_t)(uint32_t)Z * (uint64_t)(uint32_t)B;
+    return (int64_t)(int32_t)(Z >> 32) * (int64_t)B + (int64_t)(lo >> 32) + irnd;
+}
+
+// Threshold on field_hi equivalent to a threshold index: for -2304 < js <= 2304,
+// [clamp(floor(hi / 2^ish), +-2304) >= js] = [hi >= js 2^ish], and since
+// |hi| < 2^62 a product that would not fit is saturated to +-2^62.
+__host__ __device__ __forceinline__ int64_t index_threshold(int js, int ish)
+{
+    const int aj = js < 0 ? -js : js;
+    // |js| < 2^12, so the product fits whenever ish <= 50; above that the
+    // 32-bit shift count 62 - ish stays in 0..11
+    const bool fits = ish <= 50 || (aj >> (62 - ish)) == 0;
+    const int64_t sat = js > 0 ? ((int64_t)1 << 62) : (js < 0 ? -((int64_t)1 << 62) : 0);
+    return fits ? (int64_t)js * ((int64_t)1 << ish) : sat;
+}
+
 // Four 0/1 bytes of a word -> four bits.
 __device__ __forceinline__ uint32_t bytes_to_nibble(uint32_t v)
 {

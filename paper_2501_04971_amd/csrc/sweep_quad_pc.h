@@ -1,0 +1,308 @@
+// Producer/consumer form of the quadratic annealing run, for launches that
+// leave SIMDs idle (one wave of 64 replicas per CU): a workgroup is one
+// consumer wave that walks the sites of its 64 replicas, plus three producer
+// waves on the CU's other SIMDs that do the part of every visit that does not
+// depend on the state, one block of 32 sites ahead:
+//
+//  * the Philox4x32-10 draw u24 of the visit (same counters as everywhere);
+//  * its threshold index j* = min{ j : Theta[j] > u24 } (Theta is
+//    non-decreasing, so x_i = [u24 < Theta[idx]] = [idx >= j*]), from the
+//    inverse of tanh checked against the table, with an exact bisection for
+//    the rare draws in its flat tails;
+//  * the threshold on the field itself: with
+//      hi = floor((Z B_t + 2^(S'-1)) / 2^32),  idx = clamp(floor(hi / 2^ish)),
+//    and -2304 < j* <= 2304, [idx >= j*] = [hi >= j* 2^ish];  |hi| < 2^62, so
+//    j* 2^ish is saturated to +-2^62 where it would not fit;
+//  * the refill of the next block's J slab.
+//
+// The consumer's visit is then field, one 32x32->64 product and a 64-bit
+// compare; the per-site thresholds arrive through a double-buffered LDS ring
+// (32 sites x 64 lanes x 8 bytes per block) and one workgroup barrier per
+// block hands buffers over.  Results are bit-identical to sweep_quad.
+#pragma once
+#include "sweep_quad.h"
+
+namespace pbit {
+
+constexpr int kCoarseBits = 12;                       // u24 buckets of 2^12
+constexpr int kCoarseLen = (1 << (24 - kCoarseBits)) + 1;
+constexpr size_t kCoarseBytes = ((size_t)kCoarseLen * 2 + 15) & ~(size_t)15;
+constexpr size_t kRingBytes = 2 * 32 * 64 * 8;
+
+template <int NB>
+constexpr size_t quad_pc_lds_bytes()
+{
+    return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 2 * (size_t)1024 * (NB + 1) + kCoarseBytes + kRingBytes;
+}
+
+// Largest array position p with th[p] <= u (th[0] = 0 <= u), by bisection.
+__device__ __forceinline__ int theta_floor_full(const int32_t *th, uint32_t u)
+{
+    int lo = 0, hi = kThetaLen - 1;
+#pragma unroll
+    for (int it = 0; it < 13; ++it) {
+        const int mid = (lo + hi + 1) >> 1;
+        const bool le = (uint32_t)th[mid] <= u;
+        const bool open = lo < hi;
+        lo = open && le ? mid : lo;
+        hi = open && !le ? mid - 1 : hi;
+    }
+    return lo;
+}
+
+// Consumer visit of site s: thresholds come from the ring.
+template <int s, int LS>
+__device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], const int64_t *ring)
+{
+    const uint32_t xo = (xc[s >> 2] >> (8 * (s & 3))) & 1u;
+    const int64_t *cur = v.rec + 4 * s;
+    const int64_t hthr = ring[s * 64 + (threadIdx.x & 63)];
+    int32_t f = v.F[s];
+    const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + s * LS);
+#pragma unroll
+    for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
+    const int64_t meta = cur[3];
+    const int64_t Z = (xo ? cur[1] : cur[0]) + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
+    const uint32_t xn = field_hi(Z, v.Bt, v.irnd) >= hthr ? 1u : 0u;
+    const int32_t delta = (int32_t)xn - (int32_t)xo;
+    xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
+    v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
+    v.g += __mul24(delta, (int32_t)meta);
+}
+
+template <int LS, int... S>
+__device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&xc)[8], const int64_t *ring,
+                                               std::integer_sequence<int, S...>)
+{
+    ((visit_site_pc<S, LS>(v, xc, ring), visit_fence<S>()), ...);
+}
+
+// Guess of the largest table position p with th[p] <= u from the inverse of
+// the generating function 2^24 (1 + tanh(j/256))/2 at u + 1/2 (hardware log2),
+// clamped so that p - 1 .. p + 2 are table positions; the caller checks it.
+__device__ __forceinline__ int theta_floor_guess(uint32_t u)
+{
+    const float v = (float)u + 0.5f;
+    const float j = 88.72283911167299f * (__log2f(v) - __log2f(16777216.0f - v));  // 128 ln 2 = 88.72...
+    const int p = (int)floorf(j) + kThetaHalf;
+    return min(max(p, 1), kThetaLen - 3);
+}
+
+// Producer p (0..2) fills the ring buffer of block blk of sweep t: Philox groups
+// g = p, p + 3, p + 6 (four sites each; producer 2 has two groups).  The table
+// position of each draw comes from theta_floor_guess, accepted only where the
+// table confirms it; the rest (flat tails, where many positions share a value)
+// is settled by an exact bisection between the coarse table's bounds.
+// ring == nullptr: slab share only (the last block, whose successor is the
+// first block of the scoring pass); jsrc == nullptr: thresholds only.
+template <int NB>
+__device__ __forceinline__ void produce_block(const DevInstance &d, int p, int t, int blk, int64_t *ring,
+                                              const int32_t *th, const uint16_t *coarse, const int64_t *site,
+                                              uint32_t kround, uint64_t m2, const int8_t *jsrc, int8_t *ldst)
+{
+    constexpr int PIECES = NB + 1;
+    const int lane = threadIdx.x & 63;
+    if (ring) {
+        const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
+        const bool third = p + 6 < 8;
+        uint32_t u[12];
+        int lo[12], hi[12];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint32_t rnd[4] = {0u, 0u, 0u, 0u};
+            if (k < 2 || third)
+                philox_block(cbase + (uint32_t)(blk * 8 + p + 3 * k), kround, m2, d.inst_id, d.seed_lo, d.seed_hi,
+                             rnd);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = 4 * k + q;
+                u[e] = rnd[q] >> 8;
+                // fast path: invert the table's generating function and check
+                // the guess and its neighbours against the table itself
+                const int g = theta_floor_guess(u[e]);
+                const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
+                               t3 = (uint32_t)th[g + 2];
+                const bool c0 = t0 <= u[e] && u[e] < t1, c1 = t1 <= u[e] && u[e] < t2, c2 = t2 <= u[e] && u[e] < t3;
+                const int found = c1 ? g : (c0 ? g - 1 : g + 1);
+                const bool ok = c0 || c1 || c2 || !(k < 2 || third);
+                const int b = (int)(u[e] >> kCoarseBits);
+                lo[e] = ok ? found : (int)coarse[b];
+                hi[e] = ok ? found : (int)coarse[b + 1];
+            }
+        }
+        // exact bisection for the lanes the fast path did not settle (the flat
+        // tails of the table)
+        for (;;) {
+            bool any = false;
+#pragma unroll
+            for (int e = 0; e < 12; ++e) any = any || lo[e] < hi[e];
+            if (__ballot(any) == 0) break;
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                if (lo[e] < hi[e]) {
+                    const int mid = (lo[e] + hi[e] + 1) >> 1;
+                    const bool le = (uint32_t)th[mid] <= u[e];
+                    lo[e] = le ? mid : lo[e];
+                    hi[e] = le ? hi[e] : mid - 1;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k < 2 || third) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int s = 4 * (p + 3 * k) + q;
+                    const uint32_t vis = (uint32_t)(site[4 * (blk * 32 + s) + 3] >> 32);
+                    const int64_t h = index_threshold(lo[4 * k + q] + 1 - kThetaHalf, d.ish);
+                    ring[s * 64 + lane] = vis ? h : INT64_MAX;
+                }
+            }
+        }
+    }
+    if (jsrc) {
+        uint4 pf[(PIECES + 2) / 3];
+#pragma unroll
+        for (int j = 0; j < (PIECES + 2) / 3; ++j)
+            pf[j] = *reinterpret_cast<const uint4 *>(jsrc + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16);
+#pragma unroll
+        for (int j = 0; j < (PIECES + 2) / 3; ++j)
+            *reinterpret_cast<uint4 *>(ldst + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16) = pf[j];
+    }
+}
+
+// One annealing run of replicas rbase + [0, 64) by a workgroup of 4 waves
+// (wave 0 consumer, waves 1-3 producers), then the scoring of the final states.
+// smem must hold quad_pc_lds_bytes<NB>() bytes.
+template <int NB>
+__device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, unsigned char *smem)
+{
+    constexpr int NP = NB * 32;
+    constexpr int LS = NP + 16;
+    constexpr int SLAB = 1024 * (NB + 1);
+    int32_t *th = reinterpret_cast<int32_t *>(smem);
+    int64_t *site = reinterpret_cast<int64_t *>(smem + kThetaBytes);
+    int8_t *slabs = reinterpret_cast<int8_t *>(smem + kThetaBytes + NP * 32);
+    uint16_t *coarse = reinterpret_cast<uint16_t *>(smem + kThetaBytes + NP * 32 + 2 * SLAB);
+    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes + NP * 32 + 2 * SLAB + kCoarseBytes);
+
+    copy_slab<NB>(d.J, 0, slabs);
+    for (int e = threadIdx.x; e < kThetaLen; e += blockDim.x) th[e] = d.theta[e];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(d.site);
+        uint4 *dst = reinterpret_cast<uint4 *>(site);
+        for (int e = threadIdx.x; e < NP * 2; e += blockDim.x) dst[e] = src[e];
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kCoarseLen; b += blockDim.x) {
+        const uint32_t u = min((uint32_t)b << kCoarseBits, (1u << 24) - 1u);
+        coarse[b] = (uint16_t)theta_floor_full(th, u);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = rbase + lane;  // every wave serves the same 64 replicas
+    const uint32_t kround = (uint32_t)d.round_k[0];
+    const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
+    const int total = d.T * NB;
+
+    if (wave > 0) produce_block<NB>(d, wave - 1, 0, 0, ring, th, coarse, site, kround, m2, nullptr, nullptr);
+    __syncthreads();
+
+    uint32_t x[NB][8];
+#pragma unroll
+    for (int p = 0; p < NB; ++p)
+#pragma unroll
+        for (int w = 0; w < 8; ++w) x[p][w] = 0u;
+
+    BlockVisit v;
+    v.th = th;
+    v.g = -(int32_t)d.b[0];
+    v.ish = d.ish;
+    v.hclo = d.hclo;
+    v.hchi = d.hchi;
+    v.irnd = d.irnd;
+    v.sg2 = d.sg2;
+    v.k2 = d.k2;
+    v.kround = kround;
+    v.inst = d.inst_id;
+    v.seed_lo = d.seed_lo;
+    v.seed_hi = d.seed_hi;
+    v.m2 = m2;
+    v.wave = wave;
+    v.nw = 1;
+
+    int buf = 0;
+    for (int c = 0; c < total; ++c) {
+        const int t = c / NB, blk = c - (c / NB) * NB;
+        if (wave == 0) {
+            const int8_t *slab = slabs + buf * SLAB;
+            v.Bt = d.Btab[t];
+            block_fields<NB>(slab, blk, x, v.F);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
+            v.rec = site + 4 * (blk * 32);
+            v.wblk = slab + blk * 32;
+            v.blk = blk;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) v.dx[w] = 0u;
+            visit_block_pc<LS>(v, x[0], ring + buf * 32 * 64, std::make_integer_sequence<int, 32>{});
+#pragma unroll
+            for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
+            rotate_chunks<NB>(x);
+        } else {
+            // the next block's thresholds and slab (after the last block: slab 0
+            // for the scoring pass, no thresholds)
+            const int t1 = (c + 1) / NB, blk1 = (c + 1) - t1 * NB;
+            produce_block<NB>(d, wave - 1, t1, blk1, c + 1 < total ? ring + (buf ^ 1) * 32 * 64 : nullptr, th,
+                              coarse, site, kround, m2, d.J + (size_t)blk1 * SLAB, slabs + (buf ^ 1) * SLAB);
+        }
+        buf ^= 1;
+        __syncthreads();
+    }
+
+    // score the final state (wave 0); all waves help refill the slabs
+    const int n = d.n, n_ext = d.n_ext;
+    const bool live = wave == 0 && r < d.R;
+    int64_t pacc = 0;
+    int32_t sval = 0;
+    // slab 0 is in buffer `buf` after the last block wrapped around
+    for (int blk = 0; blk < NB; ++blk) {
+        const int8_t *slab = slabs + buf * SLAB;
+        if (blk + 1 < NB) copy_slab<NB>(d.J, blk + 1, slabs + (buf ^ 1) * SLAB);
+        if (wave == 0) {
+            int32_t F[32];
+            block_fields<NB>(slab, blk, x, F);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
+            uint32_t bits = 0;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) bits |= bytes_to_nibble(x[0][w]) << (4 * w);
+            if (live && blk < d.words) d.rx[(int64_t)r * d.words + blk] = bits;
+#pragma unroll
+            for (int s = 0; s < 32; ++s) {
+                const int i = blk * 32 + s;
+                const int32_t xb = (int32_t)((bits >> s) & 1u);
+                if (i < n) {
+                    const int32_t v2 = 2 * d.hprof[i] + F[s];
+                    pacc += (int64_t)(v2 & -xb);
+                } else if (i < n_ext) {
+                    sval += xb << (i - n);
+                }
+            }
+#pragma unroll
+            for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
+            rotate_chunks<NB>(x);
+        }
+        buf ^= 1;
+        __syncthreads();
+    }
+    if (live) {
+        d.rprofit[r] = pacc / 2;
+        d.rfeas[r] = v.g <= sval ? 1 : 0;
+        d.rg[r] = v.g;
+    }
+}
+
+}  // namespace pbit

@@ -5,7 +5,9 @@
 // mismatches and exits nonzero if there is any.
 #include <cstdio>
 #include <cstdint>
+#include <algorithm>
 #include <random>
+#include <vector>
 
 #include "../paper_2501_04971_amd/csrc/device_common.h"
 
@@ -55,6 +57,38 @@ int main()
             }
         }
     }
-    std::printf("checked %ld cases, %ld mismatches\n", total, bad);
-    return bad ? 1 : 0;
+    // The split kernel's decision: with Theta non-decreasing, Theta[-2304] = 0
+    // and Theta[2304] = 2^24, [u < Theta[idx]] = [field_hi >= index_threshold(j*)]
+    // with j* = min{ j : Theta[j] > u }.
+    std::vector<int32_t> th(4609);
+    for (int j = -2304; j <= 2304; ++j)
+        th[j + 2304] = (int32_t)llroundl(16777216.0L * (1.0L + tanhl((long double)j / 256.0L)) / 2.0L);
+    th[0] = 0;
+    th[4608] = 1 << 24;
+    long bad2 = 0, total2 = 0;
+    for (int S = 34; S <= 94; ++S) {
+        const int ish = S - 32;
+        const int64_t irnd = (int64_t)1 << (S - 33);
+        const int32_t hclo = ish <= 31 ? -(int32_t)(1u << (ish - 1)) : INT32_MIN;
+        const int32_t hchi = ish <= 31 ? (int32_t)((1u << (ish - 1)) - 1u) : INT32_MAX;
+        for (int it = 0; it < 20000; ++it) {
+            const int32_t B = it == 0 ? 0 : (int32_t)(rng() >> 33);
+            const int64_t Z = (int64_t)(rng() >> (2 + rng() % 60)) * ((rng() & 1) ? 1 : -1);
+            uint32_t u = (uint32_t)(rng() >> 40);
+            if (it % 7 == 0) u = (uint32_t)th[rng() % 4609] - (uint32_t)(rng() % 2);  // on table steps
+            u &= 0xFFFFFFu;
+            const int q = pbit::theta_index(Z, B, ish, irnd, hclo, hchi);
+            const bool ref = u < (uint32_t)th[q + 2304];
+            const int p = (int)(std::upper_bound(th.begin(), th.end(), (int32_t)u) - th.begin()) - 1;
+            const bool got = pbit::field_hi(Z, B, irnd) >= pbit::index_threshold(p + 1 - 2304, ish);
+            ++total2;
+            if (ref != got) {
+                if (bad2 < 10) std::printf("split mismatch S=%d Z=%lld B=%d u=%u\n", S, (long long)Z, B, u);
+                ++bad2;
+            }
+        }
+    }
+    std::printf("checked %ld cases, %ld mismatches; split form %ld cases, %ld mismatches\n", total, bad, total2,
+                bad2);
+    return bad || bad2 ? 1 : 0;
 }

@@ -1,6 +1,8 @@
 """The GPU kernels' threshold-index arithmetic (a 96-bit product split into
 32-bit pieces, a clamp and one 64-bit shift), compiled for the host and checked
-against the 128-bit definition."""
+against the 128-bit definition; and the split kernel's equivalent decision (a
+threshold on the product from the inverse of the table), checked against the
+table lookup for every shift the instance compiler can choose."""
 import os
 import shutil
 import subprocess

@@ -187,7 +187,7 @@ def test_every_tiling_is_bit_identical(need_gpu, case):
     if case == "qkp97":
         prob = G.qkp(97, Fraction(3, 4), G.rng_for(950, 0))
         par = G.Params(replicas=300, sweeps=30, beta=Fraction(5), eta=Fraction(20))
-        layouts = [(1, -1), (4, -1)]
+        layouts = [(1, -1, 0), (4, -1, 0), (4, -1, 1)]
     else:
         if case == "mkp120x12wide":
             rng = G.rng_for(950, 3)
@@ -198,13 +198,13 @@ def test_every_tiling_is_bit_identical(need_gpu, case):
             m = 5 if case == "mkp100x5" else 30
             prob = G.mkp(100, m, G.rng_for(950, m))
         par = G.Params(replicas=300, sweeps=25, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
-        layouts = [(1, 0), (1, 1), (2, 1), (3, 0), (4, 1), (4, 0)]
+        layouts = [(1, 0, 0), (1, 1, 0), (2, 1, 0), (3, 0, 0), (4, 1, 0), (4, 0, 0)]
     ref = O.saim(prob, par, 2, nthreads=NTHREADS)
     prog = ref["program"]
-    for wpb, res in layouts:
-        say(f"[tiling] {case} waves/block={wpb} lds_resident={res}")
+    for wpb, res, split in layouts:
+        say(f"[tiling] {case} waves/block={wpb} lds_resident={res} split={split}")
         inst = B.Instance(prob, par)
-        inst.set_tiling(wpb, res)
+        inst.set_tiling(wpb, res, split)
         for k in range(2):
             lam = inst.get_lambda()
             inst.sample_round()
