@@ -41,6 +41,11 @@ SIMDS = 256 * 4
 MFMA_I8_PEAK = 5.0e15
 LDS_PEAK = 256 * 128 * 2.4e9
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2)
+# and WRITE_SIZE (x1) passes (calibrated on a 256 MiB copy); valid for the
+# kernel build they were taken on, keyed by kernel and workload.
+MEASURED_TRAFFIC = {}
+
 WORKLOAD_NAMES = {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10", 2: "QKP N=300 d=1.0",
                   3: "mixed batch: 256 QKP + 256 MKP, 256 replicas each"}
 
@@ -76,7 +81,7 @@ def cpu_baseline(members, seconds_target: float = 10.0):
         O.sa_round(prog, [0] * prog.m, 0, 0, threads, threads)
         dt = time.perf_counter() - t0
         budget = seconds_target / len(members)
-        reps = threads * max(1, min(8, int(budget / max(dt, 1e-3))))
+        reps = threads * max(1, min(64, int(budget / max(dt, 1e-3))))
         t0 = time.perf_counter()
         O.sa_round(prog, [0] * prog.m, 0, threads, reps, threads)
         dt = time.perf_counter() - t0
@@ -87,6 +92,25 @@ def cpu_baseline(members, seconds_target: float = 10.0):
             "sample": f"round 0 of: {'; '.join(desc)} ({visits_all:.3g} updates, {t_all:.1f} s)"}
 
 
+def learned_start_summary(count: int = 64, rounds: int = 150):
+    """Samples to reach the plain loop's best feasible profit (less 0.1 %),
+    plain start (lambda_0 = 0) against the shipped set encoder's start, on
+    held-out QKP instances (half N=300 d=1, half N in U{100..300})."""
+    from paper_2501_04971_amd import learn as L
+    import numpy as np
+    if not os.path.exists(L.DEFAULT_WEIGHTS):
+        return None
+    ms = [L.learn_instance(L.EVAL_SEED_BASE + 20000 + i) for i in range(count)]
+    probs, pars = [p for p, _ in ms], [q for _, q in ms]
+    lam0 = L.predict_lambda0(probs, pars).cpu().numpy().reshape(count, 32)
+    plain = L.run_loop(probs, pars, rounds, log=lambda *a: None)
+    learned = L.run_loop(probs, pars, rounds, lambda0=lam0, log=lambda *a: None)
+    res = L.compare(plain, learned, rounds, pars[0].replicas)
+    res.update({"instances": count, "replicas": pars[0].replicas, "sweeps": pars[0].sweeps,
+                "unit": "samples (annealing runs of 1000 sweeps)"})
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +119,7 @@ def main() -> int:
     ap.add_argument("--workload", type=int, default=2, choices=[0, 1, 2, 3])
     ap.add_argument("--instance", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the samples-to-target comparison")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -178,10 +203,13 @@ def main() -> int:
                "sweeps_per_round": "QKP 1000, MKP 2000", "updates_per_step": updates_per_step,
                "parallelism": "one GPU, persistent work queue over (instance, 256-replica tile)"}
     else:
-        waves = (par.replicas + 63) // 64
+        groups = (par.replicas + 63) // 64
+        split = info.variant == 0 and groups <= torch.cuda.get_device_properties(0).multi_processor_count
+        waves = 4 * groups if split else groups
         best = runner.best_feasible()
-        kernel = "sweep_quad (annealing run + round epilogue)" if info.variant == 0 else \
-            "sweep_linear (annealing run + round epilogue)"
+        nb = info.n_pad // 32
+        kernel = (f"sweep_quad_pc<{nb}>" if split else f"sweep_quad<{nb}>") if info.variant == 0 else \
+            f"sweep_linear<{info.m}>"
         secondary = quad_secondary(info, updates_per_step, launch_ms / 1e3) if info.variant == 0 else {}
         cfg = {"workload": WORKLOAD_NAMES[args.workload], "n_ext": info.n_ext, "constraints": info.m,
                "replicas": par.replicas, "sweeps_per_round": par.sweeps,
@@ -209,7 +237,8 @@ def main() -> int:
             "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (32-bit integer)",
             "frac": achieved / ALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": None if batch else MEASURED_TRAFFIC.get((kernel, args.workload)),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "ops_per_update": None if batch else alu_ops_per_update(info.m),
             "launch_ms": launch_ms,
             "waves": waves,
@@ -219,6 +248,8 @@ def main() -> int:
         "wall_s": wall,
         "best_feasible_profit": None if best is None else best[0],
     }
+    if not args.no_learned and args.workload == 2:
+        out["samples_to_target"] = learned_start_summary()
     if not args.no_cpu_baseline:
         if batch:
             out["cpu_baseline"] = cpu_baseline([members[0][:2], members[1][:2]])

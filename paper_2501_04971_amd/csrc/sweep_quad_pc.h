@@ -62,8 +62,9 @@ __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], 
 #pragma unroll
     for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
     const int64_t meta = cur[3];
-    const int64_t Z = (xo ? cur[1] : cur[0]) + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
-    const uint32_t xn = field_hi(Z, v.Bt, v.irnd) >= hthr ? 1u : 0u;
+    // v.k2 holds -k2 here; the ring holds the threshold less the rounding term
+    const int64_t Z = (xo ? cur[1] : cur[0]) + (int64_t)(f * 256) * v.sg2 + (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
+    const uint32_t xn = field_hi(Z, v.Bt, 0) >= hthr ? 1u : 0u;
     const int32_t delta = (int32_t)xn - (int32_t)xo;
     xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
     v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
@@ -154,7 +155,7 @@ __device__ __forceinline__ void produce_block(const DevInstance &d, int p, int t
                 for (int q = 0; q < 4; ++q) {
                     const int s = 4 * (p + 3 * k) + q;
                     const uint32_t vis = (uint32_t)(site[4 * (blk * 32 + s) + 3] >> 32);
-                    const int64_t h = index_threshold(lo[4 * k + q] + 1 - kThetaHalf, d.ish);
+                    const int64_t h = index_threshold(lo[4 * k + q] + 1 - kThetaHalf, d.ish) - d.irnd;
                     ring[s * 64 + lane] = vis ? h : INT64_MAX;
                 }
             }
@@ -224,7 +225,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     v.hchi = d.hchi;
     v.irnd = d.irnd;
     v.sg2 = d.sg2;
-    v.k2 = d.k2;
+    v.k2 = (int64_t)(int32_t)(-d.k2);  // 0 <= k2 < 2^31, so -k2 is an int32
     v.kround = kround;
     v.inst = d.inst_id;
     v.seed_lo = d.seed_lo;
