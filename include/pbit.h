@@ -184,24 +184,25 @@ pbit_status pbit_instance_info(const pbit_instance *inst, pbit_plan_info *out);
  * kernel 1..4; 0 = the default for the replica count).  lds_resident selects,
  * for the linear kernel, whether the per-site field constants and coefficient
  * rows are staged in LDS (1), read from global memory (0), or staged whenever
- * they fit (-1, the default); ignored by the quadratic kernel.  split selects,
- * for the quadratic kernel, workgroups of one visiting wave plus three waves
- * that precompute its random draws, thresholds and J slabs (1), plain
- * workgroups (0), or the split form whenever the replicas leave CUs idle (-1,
- * the default); 1 is rejected for the linear kernel.  Every layout gives
- * bit-identical results; only the speed differs.  Host only, takes effect at
- * the next pbit_sample_round.  PBIT_ERANGE if lds_resident = 1 does not fit
- * the 160 KB of LDS at this tiling. */
+ * they fit (-1, the default); ignored by the quadratic kernel.  split selects
+ * workgroups of one visiting wave plus three waves that precompute its random
+ * draws and thresholds (and, for the quadratic kernel, its J slabs) (1), plain
+ * workgroups (0), or the split form whenever the replicas leave CUs idle and
+ * it fits LDS (-1, the default).  Every layout gives bit-identical results;
+ * only the speed differs.  Host only, takes effect at the next
+ * pbit_sample_round.  PBIT_ERANGE if lds_resident = 1 or split = 1 does not
+ * fit the 160 KB of LDS. */
 pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_t lds_resident, int32_t split);
 
 /* ---- Batched execution --------------------------------------------------
  * A batch runs many independent instances, of either kind and of uneven
  * sizes, each with its own parameters (Tables 2-5 solve every instance on its
  * own, so batching changes no result).  One round of the batch is one
- * persistent kernel launch: workgroups of 256 replicas take work items
- * (instance, replica tile) from a queue sorted by decreasing estimated cost
- * through an atomic counter; then the round epilogue and the multiplier step
- * run for every instance that still has rounds in its budget.  Every member
+ * persistent kernel launch per body family (quadratic, linear): workgroups of
+ * 256 replicas take work items (instance, replica tile) from the family's
+ * queue, sorted by decreasing estimated cost, through an atomic counter; then
+ * the round epilogue and the multiplier step run for every instance that
+ * still has rounds in its budget.  Every member
  * produces exactly what a single instance created from the same problem and
  * parameters produces.  Multi-knapsack members whose constraint count has no
  * compiled batch body (1-6, 8, 10, 16, 30 and 32 do) are padded with empty
@@ -215,7 +216,8 @@ size_t pbit_batch_workspace_bytes(const pbit_problem *probs, const pbit_params *
 /* Creates a batch in dev_ws (caller-owned device memory, 256-byte aligned, at
  * least pbit_batch_workspace_bytes).  rounds[i] is member i's round budget
  * (NULL: unlimited); a member whose budget is spent is skipped by later rounds.
- * blocks is the persistent grid size (0: one workgroup per resident slot).
+ * blocks caps the persistent grid of each kernel family (0: one workgroup per
+ * resident slot).
  * Errors as pbit_create_instance; the message names the failing member. */
 pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *params, int32_t count,
                               const int32_t *rounds, int32_t blocks, void *dev_ws, size_t ws_bytes,

@@ -6,8 +6,8 @@ purely a speed question, answered by measurement:
 
 * single instances: waves of 64 replicas per workgroup (quadratic kernel 1 or
   4; linear kernel 1..4), for the linear kernel whether the per-site
-  constants are staged in LDS or read from global memory, and for the
-  quadratic kernel the producer/consumer split;
+  constants are staged in LDS or read from global memory, and the
+  producer/consumer split;
 * batches: the persistent grid size.
 
 A probe run with a reduced sweep count times each candidate (the cost of a
@@ -51,7 +51,7 @@ def candidates(info):
     """(waves per workgroup, LDS residency, split) triples."""
     if info.variant == 0:
         return [(1, -1, 0), (4, -1, 0), (4, -1, 1)]
-    return [(w, r, 0) for w in (1, 2, 3, 4) for r in (0, 1)]
+    return [(w, r, 0) for w in (1, 2, 3, 4) for r in (0, 1)] + [(4, 1, 1)]
 
 
 def load_cache(path: str | None = None) -> dict:

@@ -25,6 +25,10 @@ SOURCES = [
     "sweep_quad_pc.hip",
     "sweep_batch.hip",
     "net_kernels.hip",
+    "sweep_linear_pc_a.hip",
+    "sweep_linear_pc_b.hip",
+    "sweep_linear_pc_c.hip",
+    "sweep_linear_pc_d.hip",
     "sweep_linear_a.hip",
     "sweep_linear_b.hip",
     "sweep_linear_c.hip",

@@ -29,6 +29,10 @@
 namespace pbit {
 hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
 hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, hipStream_t stream);
+hipError_t launch_sweep_linear_pc_a(const DevInstance &d, bool wide, hipStream_t stream);
+hipError_t launch_sweep_linear_pc_b(const DevInstance &d, bool wide, hipStream_t stream);
+hipError_t launch_sweep_linear_pc_c(const DevInstance &d, bool wide, hipStream_t stream);
+hipError_t launch_sweep_linear_pc_d(const DevInstance &d, bool wide, hipStream_t stream);
 hipError_t launch_sweep_linear_a(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
 hipError_t launch_sweep_linear_b(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
 hipError_t launch_sweep_linear_c(const DevInstance &d, bool wide, int wpb, bool resident, hipStream_t stream);
@@ -39,10 +43,10 @@ hipError_t launch_lambda_update(const DevInstance &d, int mode, const int32_t *v
 hipError_t launch_round_reduce_batch(const DevInstance *insts, int count, hipStream_t stream);
 hipError_t launch_lambda_update_batch(const DevInstance *insts, int count, int mode, hipStream_t stream);
 hipError_t launch_reset_counter(int *counter, hipStream_t stream);
-hipError_t launch_sweep_batch(const DevInstance *insts, const int4 *items, int n_items, int *counter,
+hipError_t launch_sweep_batch(bool linear, const DevInstance *insts, const int4 *items, int n_items, int *counter,
                               int blocks, size_t lds, hipStream_t stream);
-hipError_t sweep_batch_prepare(size_t lds, int *blocks_per_cu);
-const void *sweep_batch_kernel();
+hipError_t sweep_batch_prepare(bool linear, size_t lds, int *blocks_per_cu);
+const void *sweep_batch_kernel(bool linear);
 const void *round_reduce_batch_kernel();
 const void *lambda_update_batch_kernel();
 const void *reset_counter_kernel();
@@ -496,6 +500,13 @@ void fill_plan_info(const Plan &P, pbit_plan_info *out)
 
 const size_t kMaxLds = 160 * 1024;
 
+// LDS of the producer/consumer linear kernel.
+size_t linear_split_bytes(const Plan &P)
+{
+    return (size_t)kThetaBytes + kCoarseBytes + kRingBytes + (size_t)(32 * P.words + 32) * 16 +
+           (size_t)P.owords * 32 * P.m * 4 + (size_t)P.words * kWave * 4;
+}
+
 // LDS of the linear kernel with LDS-resident site constants for wpb waves.
 size_t resident_bytes(const Plan &P, int wpb)
 {
@@ -522,7 +533,7 @@ struct pbit_instance {
     int device = 0;
     int wpb = 1;
     int resident = -1;    // linear kernels: 1 LDS-resident constants, 0 global, -1 whichever fits
-    int split = -1;       // quadratic kernel: 1 producer/consumer workgroups, 0 not, -1 when CUs would idle
+    int split = -1;       // 1 producer/consumer workgroups, 0 not, -1 when CUs would idle (and LDS fits)
     int cus = 256;
     bool broken = false;
     bool member = false;  // owned by a batch
@@ -535,7 +546,10 @@ struct pbit_batch {
     std::vector<int32_t> rounds;       // initial budgets
     DevInstance *d_insts = nullptr;
     int4 *d_items = nullptr;
-    int *d_counter = nullptr;
+    int *d_counter = nullptr;          // [2]: quadratic, linear queue
+    int n_quad = 0;                    // items [0, n_quad) quadratic, the rest linear
+    int blocks_lin = 0;
+    size_t lds_lin = 0;
     int32_t *d_rounds = nullptr;
     int blocks = 0;
     size_t lds = 0;
@@ -726,7 +740,7 @@ pbit_status batch_sizes(const pbit_problem *probs, const pbit_params *params, in
             (P.variant != kQuad && resident_bytes(P, 4) > kMaxLds))
             return fail(PBIT_ERANGE, "member " + std::to_string(i) + ": no batch body for this instance shape");
         z.member_bytes.push_back(P.L.total);
-        items += (size_t)(P.R + 255) / 256;
+        items += (size_t)(P.variant == kQuad ? (P.R + 255) / 256 : (P.R + 63) / 64);  // split tiles hold 64
     }
     size_t o = 0;
     auto put = [&o](size_t bytes) {
@@ -736,7 +750,7 @@ pbit_status batch_sizes(const pbit_problem *probs, const pbit_params *params, in
     };
     z.off_insts = put((size_t)count * sizeof(DevInstance));
     z.off_items = put(items * sizeof(int4));
-    z.off_counter = put(4);
+    z.off_counter = put(8);
     z.off_rounds = put((size_t)count * 4);
     for (int i = 0; i < count; ++i) z.off_member.push_back(put(z.member_bytes[i]));
     z.total = o;
@@ -757,48 +771,53 @@ pbit_status batch_error(pbit_batch *b, hipError_t e, const char *what)
     return fail(PBIT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// The four launches of one batch round as a graph of kernel nodes in a chain
-// (the work-queue counter is cleared by a kernel, not a memset node).
+// One batch round as a graph of kernel nodes: counter reset, the two family
+// kernels side by side, round reduce, multiplier step (the work-queue
+// counters are cleared by a kernel, not a memset node).
 hipError_t build_round_graph(pbit_batch *b)
 {
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);
     if (e != hipSuccess) return e;
     DevInstance *insts = b->d_insts;
-    int4 *items = b->d_items;
-    int *counter = b->d_counter;
-    int n_items = (int)b->items.size();
+    int4 *items_q = b->d_items;
+    int4 *items_l = b->d_items + b->n_quad;
+    int *counter_q = b->d_counter;
+    int *counter_l = b->d_counter + 1;
+    int n_quad = b->n_quad;
+    int n_lin = (int)b->items.size() - b->n_quad;
     int mode = 1;
-    void *a_reset[] = {&counter};
-    void *a_sweep[] = {&insts, &items, &n_items, &counter};
+    void *a_reset[] = {&counter_q};
+    void *a_lin[] = {&insts, &items_l, &n_lin, &counter_l};
+    void *a_quad[] = {&insts, &items_q, &n_quad, &counter_q};
     void *a_reduce[] = {&insts};
     void *a_lambda[] = {&insts, &mode};
     const int count = (int)b->members.size();
-    struct Node {
-        const void *func;
-        dim3 grid, block;
-        size_t lds;
-        void **args;
-    } nodes[4] = {
-        {reset_counter_kernel(), dim3(1), dim3(64), 0, a_reset},
-        {sweep_batch_kernel(), dim3(b->blocks), dim3(256), b->lds, a_sweep},
-        {round_reduce_batch_kernel(), dim3(count), dim3(reduce_threads()), 0, a_reduce},
-        {lambda_update_batch_kernel(), dim3(count), dim3(256), 0, a_lambda},
-    };
-    hipGraphNode_t prev = nullptr;
-    for (const Node &nd : nodes) {
+    auto add = [&](const void *func, dim3 grid, dim3 block, size_t lds, void **args, const hipGraphNode_t *deps,
+                   size_t ndeps, hipGraphNode_t *node) {
         hipKernelNodeParams p{};
-        p.func = const_cast<void *>(nd.func);
-        p.gridDim = nd.grid;
-        p.blockDim = nd.block;
-        p.sharedMemBytes = (unsigned)nd.lds;
-        p.kernelParams = nd.args;
+        p.func = const_cast<void *>(func);
+        p.gridDim = grid;
+        p.blockDim = block;
+        p.sharedMemBytes = (unsigned)lds;
+        p.kernelParams = args;
         p.extra = nullptr;
-        hipGraphNode_t node = nullptr;
-        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-        if (e != hipSuccess) break;
-        prev = node;
-    }
+        return hipGraphAddKernelNode(node, g, deps, ndeps, &p);
+    };
+    // reset -> {linear family, quadratic family} -> reduce -> multiplier step;
+    // the two family kernels are independent nodes and run side by side
+    hipGraphNode_t reset = nullptr, sweeps[2] = {nullptr, nullptr}, reduce = nullptr, lambda = nullptr;
+    size_t nsweep = 0;
+    e = add(reset_counter_kernel(), dim3(1), dim3(64), 0, a_reset, nullptr, 0, &reset);
+    if (e == hipSuccess && n_lin > 0)
+        e = add(sweep_batch_kernel(true), dim3(b->blocks_lin), dim3(256), b->lds_lin, a_lin, &reset, 1, &sweeps[nsweep++]);
+    if (e == hipSuccess && n_quad > 0)
+        e = add(sweep_batch_kernel(false), dim3(b->blocks), dim3(256), b->lds, a_quad, &reset, 1, &sweeps[nsweep++]);
+    if (e == hipSuccess)
+        e = add(round_reduce_batch_kernel(), dim3(count), dim3(reduce_threads()), 0, a_reduce,
+                nsweep ? sweeps : &reset, nsweep ? nsweep : 1, &reduce);
+    if (e == hipSuccess)
+        e = add(lambda_update_batch_kernel(), dim3(count), dim3(256), 0, a_lambda, &reduce, 1, &lambda);
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         hipGraphDestroy(g);
@@ -906,6 +925,16 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
         }
         default: {
             const bool wide = inst->plan.variant == kLinearWide;
+            const bool split = inst->split == 1 ||
+                               (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus &&
+                                linear_split_bytes(inst->plan) <= kMaxLds);
+            if (split) {
+                if (d.m <= 6) e = launch_sweep_linear_pc_a(d, wide, s);
+                else if (d.m <= 12) e = launch_sweep_linear_pc_b(d, wide, s);
+                else if (d.m <= 20) e = launch_sweep_linear_pc_c(d, wide, s);
+                else e = launch_sweep_linear_pc_d(d, wide, s);
+                break;
+            }
             const bool res = inst->resident == 1 ||
                              (inst->resident < 0 && resident_bytes(inst->plan, inst->wpb) <= kMaxLds);
             if (d.m <= 6) e = launch_sweep_linear_a(d, wide, inst->wpb, res, s);
@@ -1030,12 +1059,14 @@ pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_
     const bool ok = quad ? (wpb == 1 || wpb == 4) : (wpb >= 1 && wpb <= 4);
     if (!ok) return fail(PBIT_EINVAL, "waves per block must be 1 or 4 (quadratic) or 1..4 (linear)");
     if (lds_resident < -1 || lds_resident > 1) return fail(PBIT_EINVAL, "lds_resident must be -1, 0 or 1");
-    if (split < -1 || split > 1 || (split == 1 && !quad)) return fail(PBIT_EINVAL, "split must be -1, 0 or 1 (1: quadratic only)");
+    if (split < -1 || split > 1) return fail(PBIT_EINVAL, "split must be -1, 0 or 1");
+    if (split == 1 && !quad && linear_split_bytes(inst->plan) > kMaxLds)
+        return fail(PBIT_ERANGE, "site constants do not fit LDS for the split layout");
     if (!quad && lds_resident == 1 && resident_bytes(inst->plan, wpb) > kMaxLds)
         return fail(PBIT_ERANGE, "site constants do not fit LDS at this tiling");
     inst->wpb = wpb;
     inst->resident = quad ? -1 : lds_resident;
-    inst->split = quad ? split : 0;
+    inst->split = split;
     return PBIT_OK;
 }
 
@@ -1075,6 +1106,8 @@ pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *para
         int4 item;
     };
     std::vector<Cost> q;
+    std::vector<int64_t> lin_cost(count, -1);
+    int64_t lin_total = 0;
     for (int i = 0; i < count; ++i) {
         pbit_instance *m = nullptr;
         st = create_impl(&z.padded[i].prob, &params[i], base + z.off_member[i], z.member_bytes[i], stream, &m);
@@ -1087,28 +1120,55 @@ pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *para
         m->dev.rounds_left = b->d_rounds + i;
         b->members.push_back(m);
         b->dev.push_back(m->dev);
-        const Plan &P = m->plan;
-        const int code = batch_variant_code(P.variant, P.nb, P.m);
-        const int64_t per_visit = P.variant == kQuad ? 96 + 8 * P.nb : 64 + 6 * P.m;
-        const int64_t cost = (int64_t)P.T * P.n_ext * per_visit;
-        for (int r0 = 0; r0 < P.R; r0 += 256)
-            q.push_back({cost, make_int4(i, r0, code, (int)std::min<int64_t>(cost >> 16, INT32_MAX))});
-        const size_t need = P.variant == kQuad
-                                ? (size_t)kThetaBytes + (size_t)P.nb * 1024 + (size_t)2048 * (P.nb + 1)
-                                : resident_bytes(P, 4);
-        b->lds = std::max(b->lds, need);
         b->rounds.push_back(rounds ? rounds[i] : INT32_MAX);
+        const Plan &P = m->plan;
+        if (P.variant != kQuad) {
+            // chain cost of a plain 256-replica tile, in visit-cycles (roughly)
+            lin_cost[i] = (int64_t)P.T * P.n_ext * (64 + 6 * P.m);
+            lin_total += lin_cost[i] * ((P.R + 255) / 256);
+        }
+    }
+    int cus = 0, dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1) cus = 1;
+    // Which linear members run as split tiles: a split tile visits about twice
+    // as fast but takes four waves per 64 replicas, i.e. twice the work per
+    // replica.  Members whose plain chain exceeds the average linear load per
+    // CU by a quarter would bound the round, so they are split (a threshold
+    // chosen by measurement on the mixed workload: splitting fewer or more
+    // members both lengthened its rounds).
+    std::vector<char> split(count, 0);
+    const int64_t load = lin_total / cus;
+    for (int i = 0; i < count; ++i)
+        split[i] = lin_cost[i] > load + load / 4 && linear_split_bytes(b->members[i]->plan) <= kMaxLds;
+    for (int i = 0; i < count; ++i) {
+        const Plan &P = b->members[i]->plan;
+        const int code = batch_variant_code(P.variant, P.nb, P.m);
+        if (P.variant == kQuad) {
+            const int64_t cost = ((int64_t)1 << 60) + (int64_t)P.T * P.n_ext * (96 + 8 * P.nb);
+            for (int r0 = 0; r0 < P.R; r0 += 256) q.push_back({cost, make_int4(i, r0, code, 0)});
+            b->lds = std::max(b->lds, (size_t)kThetaBytes + (size_t)P.nb * 1024 + (size_t)2048 * (P.nb + 1));
+            b->n_quad += (P.R + 255) / 256;
+        } else if (split[i]) {
+            const int64_t cost = lin_cost[i] / 2;
+            for (int r0 = 0; r0 < P.R; r0 += 64) q.push_back({cost, make_int4(i, r0, code | kBatchSplit, 0)});
+            b->lds_lin = std::max(b->lds_lin, linear_split_bytes(P));
+        } else {
+            for (int r0 = 0; r0 < P.R; r0 += 256) q.push_back({lin_cost[i], make_int4(i, r0, code, 0)});
+            b->lds_lin = std::max(b->lds_lin, resident_bytes(P, 4));
+        }
     }
     std::stable_sort(q.begin(), q.end(), [](const Cost &x, const Cost &y) { return x.cost > y.cost; });
     for (const Cost &c : q) b->items.push_back(c.item);
 
-    int per_cu = 0, cus = 0, dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = sweep_batch_prepare(b->lds, &per_cu);
-    if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
-    const int n_items = (int)b->items.size();
-    b->blocks = blocks > 0 ? blocks : std::min(n_items, cus * per_cu);
+    int per_cu = 1, per_cu_lin = 1;
+    const int n_quad = b->n_quad, n_lin = (int)b->items.size() - b->n_quad;
+    if (e == hipSuccess && n_quad > 0) e = sweep_batch_prepare(false, b->lds, &per_cu);
+    if (e == hipSuccess && n_lin > 0) e = sweep_batch_prepare(true, b->lds_lin, &per_cu_lin);
+    if (e == hipSuccess && (per_cu < 1 || per_cu_lin < 1)) e = hipErrorInvalidConfiguration;
+    b->blocks = n_quad == 0 ? 0 : (blocks > 0 ? std::min(blocks, n_quad) : std::min(n_quad, cus * per_cu));
+    b->blocks_lin = n_lin == 0 ? 0 : (blocks > 0 ? std::min(blocks, n_lin) : std::min(n_lin, cus * per_cu_lin));
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_insts, b->dev.data(), b->dev.size() * sizeof(DevInstance), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -1132,9 +1192,13 @@ pbit_status pbit_batch_sample_round(pbit_batch *b, pbit_stream stream)
     if (st != PBIT_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int count = (int)b->members.size();
+    const int n_lin = (int)b->items.size() - b->n_quad;
     hipError_t e = launch_reset_counter(b->d_counter, s);
-    if (e == hipSuccess)
-        e = launch_sweep_batch(b->d_insts, b->d_items, (int)b->items.size(), b->d_counter, b->blocks, b->lds, s);
+    if (e == hipSuccess && b->n_quad > 0)
+        e = launch_sweep_batch(false, b->d_insts, b->d_items, b->n_quad, b->d_counter, b->blocks, b->lds, s);
+    if (e == hipSuccess && n_lin > 0)
+        e = launch_sweep_batch(true, b->d_insts, b->d_items + b->n_quad, n_lin, b->d_counter + 1, b->blocks_lin,
+                               b->lds_lin, s);
     if (e == hipSuccess) e = launch_round_reduce_batch(b->d_insts, count, s);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return batch_error(b, e, "batch sample_round launch failed");
@@ -1201,8 +1265,8 @@ pbit_status pbit_batch_shape(const pbit_batch *b, int32_t *items, int32_t *block
 {
     if (!b) return fail(PBIT_EINVAL, "null batch");
     if (items) *items = (int32_t)b->items.size();
-    if (blocks) *blocks = b->blocks;
-    if (lds_bytes) *lds_bytes = b->lds;
+    if (blocks) *blocks = b->blocks + b->blocks_lin;
+    if (lds_bytes) *lds_bytes = std::max(b->lds, b->lds_lin);
     return PBIT_OK;
 }
 

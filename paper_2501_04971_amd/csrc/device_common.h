@@ -94,6 +94,23 @@ __host__ __device__ __forceinline__ int64_t index_threshold(int js, int ish)
     return fits ? (int64_t)js * ((int64_t)1 << ish) : sat;
 }
 
+// 24-bit signed multiply (-add) on the vector ALU.  The instructions read only
+// the low 24 bits of each operand, so values known to lie in [-2^23, 2^23) need
+// no sign extension first (which __mul24 spells out for arbitrary ints).
+__device__ __forceinline__ int32_t mul_i24(int32_t a, int32_t b)
+{
+    int32_t r;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ int32_t mad_i24(int32_t a, int32_t b, int32_t c)
+{
+    int32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // Four 0/1 bytes of a word -> four bits.
 __device__ __forceinline__ uint32_t bytes_to_nibble(uint32_t v)
 {

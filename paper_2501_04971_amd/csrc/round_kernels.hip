@@ -208,9 +208,10 @@ hipError_t launch_batch_snapshot(const DevInstance *insts, int count, unsigned c
                            stream);
 }
 
+// Clears the work-queue counters (both families).
 __global__ void reset_counter(int *counter)
 {
-    if (threadIdx.x == 0) *counter = 0;
+    if (threadIdx.x < 2) counter[threadIdx.x] = 0;
 }
 
 const void *round_reduce_batch_kernel() { return reinterpret_cast<const void *>(&round_reduce_batch); }

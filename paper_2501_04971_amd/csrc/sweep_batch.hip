@@ -1,28 +1,32 @@
-// Persistent annealing kernel for a batch of instances of different kinds and
+// Persistent annealing kernels for a batch of instances of different kinds and
 // sizes: every workgroup (4 waves = 256 replicas) takes work items (instance,
 // first replica, kernel variant) from a queue ordered by decreasing estimated
 // cost through one atomic counter, runs the annealing run of that replica
 // tile with the body of the matching variant, and takes the next item until
-// the queue is empty.  All items of a round are independent, so the order in
-// which workgroups take them changes no result.
-#include "sweep_linear.h"
+// the queue is empty.  Quadratic and linear items have a kernel and a queue
+// each.  All items of a round are independent, so the order in which
+// workgroups take them changes no result.
+#include "sweep_linear_pc.h"
 #include "sweep_quad.h"
 
 namespace pbit {
 
-// Each variant body is inlined into the one kernel.  The items of a round
-// are bound by their longest replica chains, not by occupancy, so the register
-// budget of the largest body (one wave per SIMD) costs little.
+// The variant bodies of a family are inlined into that family's kernel.
 template <int NB>
 __device__ __forceinline__ void batch_quad(const DevInstance &d, int rbase, unsigned char *smem)
 {
     quad_run<NB, 4, false>(d, rbase, smem);
 }
 
+// A linear item is either a plain tile (4 waves visiting 256 replicas) or a
+// split tile (one wave visiting 64 replicas, three precomputing its draws and
+// thresholds); the host gives the split form to the members whose chains are
+// long enough to bound the round.
 template <int M, bool WIDE>
-__device__ __forceinline__ void batch_linear(const DevInstance &d, int rbase, unsigned char *smem)
+__device__ __forceinline__ void batch_linear(const DevInstance &d, int rbase, bool split, unsigned char *smem)
 {
-    linear_run_lds<M, WIDE>(d, rbase, smem);
+    if (split) linear_run_pc<M, WIDE>(d, rbase, smem);
+    else linear_run_lds<M, WIDE>(d, rbase, smem);
 }
 
 #define PBIT_BQ(nb)                                                                         \
@@ -31,12 +35,15 @@ __device__ __forceinline__ void batch_linear(const DevInstance &d, int rbase, un
         break;
 #define PBIT_BL(idx, mm)                                                                    \
     case 32 + 2 * idx:                                                                      \
-        batch_linear<mm, false>(insts[item.x], item.y, smem);                                          \
+        batch_linear<mm, false>(insts[item.x], item.y, split, smem);                        \
         break;                                                                              \
     case 33 + 2 * idx:                                                                      \
-        batch_linear<mm, true>(insts[item.x], item.y, smem);                                           \
+        batch_linear<mm, true>(insts[item.x], item.y, split, smem);                         \
         break;
 
+// LINEAR = false serves the quadratic items, true the linear ones: two
+// kernels, so that each family of bodies is register-allocated on its own.
+template <bool LINEAR>
 __global__ __launch_bounds__(256) void sweep_batch(
     const DevInstance *__restrict__ insts, const int4 *__restrict__ items, int n_items, int *__restrict__ counter)
 {
@@ -51,19 +58,30 @@ __global__ __launch_bounds__(256) void sweep_batch(
         const int4 item = items[it];  // instance, first replica, variant, estimated cost
         const int *left = insts[item.x].rounds_left;
         if (left && left[0] <= 0) continue;
-        switch (item.z) {
-            PBIT_BQ(1) PBIT_BQ(2) PBIT_BQ(3) PBIT_BQ(4) PBIT_BQ(5) PBIT_BQ(6)
-            PBIT_BQ(7) PBIT_BQ(8) PBIT_BQ(9) PBIT_BQ(10) PBIT_BQ(11)
-            PBIT_BL(0, 1) PBIT_BL(1, 2) PBIT_BL(2, 3) PBIT_BL(3, 4) PBIT_BL(4, 5) PBIT_BL(5, 6)
-            PBIT_BL(6, 8) PBIT_BL(7, 10) PBIT_BL(8, 16) PBIT_BL(9, 30) PBIT_BL(10, 32)
-            default:
-                break;
+        if constexpr (!LINEAR) {
+            switch (item.z) {
+                PBIT_BQ(1) PBIT_BQ(2) PBIT_BQ(3) PBIT_BQ(4) PBIT_BQ(5) PBIT_BQ(6)
+                PBIT_BQ(7) PBIT_BQ(8) PBIT_BQ(9) PBIT_BQ(10) PBIT_BQ(11)
+                default:
+                    break;
+            }
+        } else {
+            const bool split = (item.z & kBatchSplit) != 0;
+            switch (item.z & ~kBatchSplit) {
+                PBIT_BL(0, 1) PBIT_BL(1, 2) PBIT_BL(2, 3) PBIT_BL(3, 4) PBIT_BL(4, 5) PBIT_BL(5, 6)
+                PBIT_BL(6, 8) PBIT_BL(7, 10) PBIT_BL(8, 16) PBIT_BL(9, 30) PBIT_BL(10, 32)
+                default:
+                    break;
+            }
         }
         __syncthreads();  // LDS is reused by the next item
     }
 }
 
-const void *sweep_batch_kernel() { return reinterpret_cast<const void *>(&sweep_batch); }
+const void *sweep_batch_kernel(bool linear)
+{
+    return linear ? reinterpret_cast<const void *>(&sweep_batch<true>) : reinterpret_cast<const void *>(&sweep_batch<false>);
+}
 
 // Constraint count of the batch body that serves m constraints (0 if none).
 int batch_linear_m(int m)
@@ -75,7 +93,8 @@ int batch_linear_m(int m)
 }
 
 // Queue code of the body for a member: NB - 1 for the quadratic body,
-// 32 + 2 idx (+1 with 64-bit dots) for the linear bodies.
+// 32 + 2 idx (+1 with 64-bit dots) for the linear bodies (kBatchSplit added
+// by the host for split tiles).
 int batch_variant_code(int variant, int nb, int m)
 {
     if (variant == kQuad) return nb >= 1 && nb <= kMaxQuadBlocks ? nb - 1 : -1;
@@ -85,19 +104,19 @@ int batch_variant_code(int variant, int nb, int m)
     return -1;
 }
 
-hipError_t sweep_batch_prepare(size_t lds, int *blocks_per_cu)
+hipError_t sweep_batch_prepare(bool linear, size_t lds, int *blocks_per_cu)
 {
-    const void *kern = sweep_batch_kernel();
+    const void *kern = sweep_batch_kernel(linear);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, 256, lds);
 }
 
-hipError_t launch_sweep_batch(const DevInstance *insts, const int4 *items, int n_items, int *counter,
+hipError_t launch_sweep_batch(bool linear, const DevInstance *insts, const int4 *items, int n_items, int *counter,
                               int blocks, size_t lds, hipStream_t stream)
 {
     void *args[] = {&insts, &items, &n_items, &counter};
-    return hipLaunchKernel(sweep_batch_kernel(), dim3(blocks), dim3(256), args, lds, stream);
+    return hipLaunchKernel(sweep_batch_kernel(linear), dim3(blocks), dim3(256), args, lds, stream);
 }
 
 }  // namespace pbit

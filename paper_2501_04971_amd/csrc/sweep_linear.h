@@ -238,9 +238,9 @@ __device__ __forceinline__ int64_t residual_dot(const int32_t *a, const int32_t 
     }
     int32_t part[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) part[p] = __mul24(a[p], g[p]);
+    for (int p = 0; p < P; ++p) part[p] = mul_i24(a[p], g[p]);
 #pragma unroll
-    for (int k = P; k < M; ++k) part[k % P] += __mul24(a[k], g[k]);
+    for (int k = P; k < M; ++k) part[k % P] = mad_i24(a[k], g[k], part[k % P]);
     int32_t t = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) t += part[p];
@@ -313,7 +313,7 @@ __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, 
                 const uint32_t xn = (rnd[s & 3] >> 8) < thr ? 1u : 0u;
                 const int32_t delta = (int32_t)xn - (int32_t)xo;
 #pragma unroll
-                for (int k = 0; k < M; ++k) g[k] += WIDE ? delta * a[k] : __mul24(delta, a[k]);
+                for (int k = 0; k < M; ++k) g[k] = WIDE ? g[k] + delta * a[k] : mad_i24(delta, a[k], g[k]);
                 xw = (xw & ~(1u << s)) | (xn << s);
             }
             xl[blk * kWave + lane] = xw;

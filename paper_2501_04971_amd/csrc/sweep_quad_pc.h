@@ -24,11 +24,6 @@
 
 namespace pbit {
 
-constexpr int kCoarseBits = 12;                       // u24 buckets of 2^12
-constexpr int kCoarseLen = (1 << (24 - kCoarseBits)) + 1;
-constexpr size_t kCoarseBytes = ((size_t)kCoarseLen * 2 + 15) & ~(size_t)15;
-constexpr size_t kRingBytes = 2 * 32 * 64 * 8;
-
 template <int NB>
 constexpr size_t quad_pc_lds_bytes()
 {
@@ -89,86 +84,93 @@ __device__ __forceinline__ int theta_floor_guess(uint32_t u)
     return min(max(p, 1), kThetaLen - 3);
 }
 
-// Producer p (0..2) fills the ring buffer of block blk of sweep t: Philox groups
-// g = p, p + 3, p + 6 (four sites each; producer 2 has two groups).  The table
-// position of each draw comes from theta_floor_guess, accepted only where the
-// table confirms it; the rest (flat tails, where many positions share a value)
-// is settled by an exact bisection between the coarse table's bounds.
-// ring == nullptr: slab share only (the last block, whose successor is the
-// first block of the scoring pass); jsrc == nullptr: thresholds only.
-template <int NB>
-__device__ __forceinline__ void produce_block(const DevInstance &d, int p, int t, int blk, int64_t *ring,
-                                              const int32_t *th, const uint16_t *coarse, const int64_t *site,
-                                              uint32_t kround, uint64_t m2, const int8_t *jsrc, int8_t *ldst)
+// Producer p (0..2) fills the ring buffer of block blk (sites 32 blk ..
+// 32 blk + 31) of sweep t: Philox groups g = p, p + 3, p + 6 (four sites each;
+// producer 2 has two groups).  The table position of each draw comes from
+// theta_floor_guess, accepted only where the table confirms it; the rest (flat
+// tails, where many positions share a value) is settled by an exact bisection
+// between the coarse table's bounds.  Sites at or beyond N_ext never flip.
+__device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, int t, int blk, int64_t *ring,
+                                                   const int32_t *th, const uint16_t *coarse, uint32_t kround,
+                                                   uint64_t m2)
 {
-    constexpr int PIECES = NB + 1;
     const int lane = threadIdx.x & 63;
-    if (ring) {
-        const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
-        const bool third = p + 6 < 8;
-        uint32_t u[12];
-        int lo[12], hi[12];
+    const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
+    const bool third = p + 6 < 8;
+    uint32_t u[12];
+    int lo[12], hi[12];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            uint32_t rnd[4] = {0u, 0u, 0u, 0u};
-            if (k < 2 || third)
-                philox_block(cbase + (uint32_t)(blk * 8 + p + 3 * k), kround, m2, d.inst_id, d.seed_lo, d.seed_hi,
-                             rnd);
+    for (int k = 0; k < 3; ++k) {
+        uint32_t rnd[4] = {0u, 0u, 0u, 0u};
+        if (k < 2 || third)
+            philox_block(cbase + (uint32_t)(blk * 8 + p + 3 * k), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = 4 * k + q;
-                u[e] = rnd[q] >> 8;
-                // fast path: invert the table's generating function and check
-                // the guess and its neighbours against the table itself
-                const int g = theta_floor_guess(u[e]);
-                const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
-                               t3 = (uint32_t)th[g + 2];
-                const bool c0 = t0 <= u[e] && u[e] < t1, c1 = t1 <= u[e] && u[e] < t2, c2 = t2 <= u[e] && u[e] < t3;
-                const int found = c1 ? g : (c0 ? g - 1 : g + 1);
-                const bool ok = c0 || c1 || c2 || !(k < 2 || third);
-                const int b = (int)(u[e] >> kCoarseBits);
-                lo[e] = ok ? found : (int)coarse[b];
-                hi[e] = ok ? found : (int)coarse[b + 1];
-            }
+        for (int q = 0; q < 4; ++q) {
+            const int e = 4 * k + q;
+            u[e] = rnd[q] >> 8;
+            // fast path: invert the table's generating function and check the
+            // guess and its neighbours against the table itself
+            const int g = theta_floor_guess(u[e]);
+            const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
+                           t3 = (uint32_t)th[g + 2];
+            const bool c0 = t0 <= u[e] && u[e] < t1, c1 = t1 <= u[e] && u[e] < t2, c2 = t2 <= u[e] && u[e] < t3;
+            const int found = c1 ? g : (c0 ? g - 1 : g + 1);
+            const bool ok = c0 || c1 || c2 || !(k < 2 || third);
+            const int b = (int)(u[e] >> kCoarseBits);
+            lo[e] = ok ? found : (int)coarse[b];
+            hi[e] = ok ? found : (int)coarse[b + 1];
         }
-        // exact bisection for the lanes the fast path did not settle (the flat
-        // tails of the table)
-        for (;;) {
-            bool any = false;
+    }
+    // exact bisection for the draws the fast path did not settle
+    for (;;) {
+        bool any = false;
 #pragma unroll
-            for (int e = 0; e < 12; ++e) any = any || lo[e] < hi[e];
-            if (__ballot(any) == 0) break;
+        for (int e = 0; e < 12; ++e) any = any || lo[e] < hi[e];
+        if (__ballot(any) == 0) break;
 #pragma unroll
-            for (int e = 0; e < 12; ++e) {
-                if (lo[e] < hi[e]) {
-                    const int mid = (lo[e] + hi[e] + 1) >> 1;
-                    const bool le = (uint32_t)th[mid] <= u[e];
-                    lo[e] = le ? mid : lo[e];
-                    hi[e] = le ? hi[e] : mid - 1;
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (k < 2 || third) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int s = 4 * (p + 3 * k) + q;
-                    const uint32_t vis = (uint32_t)(site[4 * (blk * 32 + s) + 3] >> 32);
-                    const int64_t h = index_threshold(lo[4 * k + q] + 1 - kThetaHalf, d.ish) - d.irnd;
-                    ring[s * 64 + lane] = vis ? h : INT64_MAX;
-                }
+        for (int e = 0; e < 12; ++e) {
+            if (lo[e] < hi[e]) {
+                const int mid = (lo[e] + hi[e] + 1) >> 1;
+                const bool le = (uint32_t)th[mid] <= u[e];
+                lo[e] = le ? mid : lo[e];
+                hi[e] = le ? hi[e] : mid - 1;
             }
         }
     }
-    if (jsrc) {
-        uint4 pf[(PIECES + 2) / 3];
 #pragma unroll
-        for (int j = 0; j < (PIECES + 2) / 3; ++j)
-            pf[j] = *reinterpret_cast<const uint4 *>(jsrc + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16);
+    for (int k = 0; k < 3; ++k) {
+        if (k < 2 || third) {
 #pragma unroll
-        for (int j = 0; j < (PIECES + 2) / 3; ++j)
-            *reinterpret_cast<uint4 *>(ldst + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16) = pf[j];
+            for (int q = 0; q < 4; ++q) {
+                const int s = 4 * (p + 3 * k) + q;
+                const int64_t h = index_threshold(lo[4 * k + q] + 1 - kThetaHalf, d.ish) - d.irnd;
+                ring[s * 64 + lane] = blk * 32 + s < d.n_ext ? h : INT64_MAX;
+            }
+        }
+    }
+}
+
+// Producer p's share of the next J slab (quadratic kernel).
+template <int NB>
+__device__ __forceinline__ void produce_slab(int p, const int8_t *jsrc, int8_t *ldst)
+{
+    constexpr int PIECES = NB + 1;
+    const int lane = threadIdx.x & 63;
+    uint4 pf[(PIECES + 2) / 3];
+#pragma unroll
+    for (int j = 0; j < (PIECES + 2) / 3; ++j)
+        pf[j] = *reinterpret_cast<const uint4 *>(jsrc + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16);
+#pragma unroll
+    for (int j = 0; j < (PIECES + 2) / 3; ++j)
+        *reinterpret_cast<uint4 *>(ldst + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16) = pf[j];
+}
+
+// Builds the coarse table of theta_floor at the bucket edges (whole workgroup).
+__device__ __forceinline__ void build_coarse(const int32_t *th, uint16_t *coarse)
+{
+    for (int b = threadIdx.x; b < kCoarseLen; b += blockDim.x) {
+        const uint32_t u = min((uint32_t)b << kCoarseBits, (1u << 24) - 1u);
+        coarse[b] = (uint16_t)theta_floor_full(th, u);
     }
 }
 
@@ -195,10 +197,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
         for (int e = threadIdx.x; e < NP * 2; e += blockDim.x) dst[e] = src[e];
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kCoarseLen; b += blockDim.x) {
-        const uint32_t u = min((uint32_t)b << kCoarseBits, (1u << 24) - 1u);
-        coarse[b] = (uint16_t)theta_floor_full(th, u);
-    }
+    build_coarse(th, coarse);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -208,7 +207,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int total = d.T * NB;
 
-    if (wave > 0) produce_block<NB>(d, wave - 1, 0, 0, ring, th, coarse, site, kround, m2, nullptr, nullptr);
+    if (wave > 0) produce_thresholds(d, wave - 1, 0, 0, ring, th, coarse, kround, m2);
     __syncthreads();
 
     uint32_t x[NB][8];
@@ -256,8 +255,8 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             // the next block's thresholds and slab (after the last block: slab 0
             // for the scoring pass, no thresholds)
             const int t1 = (c + 1) / NB, blk1 = (c + 1) - t1 * NB;
-            produce_block<NB>(d, wave - 1, t1, blk1, c + 1 < total ? ring + (buf ^ 1) * 32 * 64 : nullptr, th,
-                              coarse, site, kround, m2, d.J + (size_t)blk1 * SLAB, slabs + (buf ^ 1) * SLAB);
+            if (c + 1 < total) produce_thresholds(d, wave - 1, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, coarse, kround, m2);
+            produce_slab<NB>(wave - 1, d.J + (size_t)blk1 * SLAB, slabs + (buf ^ 1) * SLAB);
         }
         buf ^= 1;
         __syncthreads();

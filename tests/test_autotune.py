@@ -20,7 +20,7 @@ def test_keys_candidates_and_cache(tmp_path):
     assert A.shape_key(iq, 300) == f"v0-n{iq.n_pad}-m1-r512"
     assert A.shape_key(im, 300).startswith("v1-n") and A.shape_key(im, 300).endswith("-m7-r512")
     assert A.candidates(iq) == [(1, -1, 0), (4, -1, 0), (4, -1, 1)]
-    assert len(A.candidates(im)) == 8
+    assert len(A.candidates(im)) == 9
     path = str(tmp_path / "t.json")
     assert A.load_cache(path) == {}
     A.save_cache({"k": {"waves_per_block": 4, "lds_resident": -1}}, path)
@@ -34,7 +34,7 @@ def test_tuned_layout_is_used_and_exact(need_gpu, tmp_path):
     prob = G.mkp(100, 5, G.rng_for(981, 0))
     par = G.Params(replicas=200, sweeps=20, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
     entry = A.tune_instance(prob, par, probe_sweeps=10, reps=1, path=path)
-    assert len(entry["probe_ms"]) == 8
+    assert len(entry["probe_ms"]) == 9
     inst = B.Instance(prob, par)
     got = A.apply(inst, prob, par, tune_missing=False, path=path)
     assert got == entry

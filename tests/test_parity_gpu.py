@@ -198,7 +198,7 @@ def test_every_tiling_is_bit_identical(need_gpu, case):
             m = 5 if case == "mkp100x5" else 30
             prob = G.mkp(100, m, G.rng_for(950, m))
         par = G.Params(replicas=300, sweeps=25, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
-        layouts = [(1, 0, 0), (1, 1, 0), (2, 1, 0), (3, 0, 0), (4, 1, 0), (4, 0, 0)]
+        layouts = [(1, 0, 0), (1, 1, 0), (2, 1, 0), (3, 0, 0), (4, 1, 0), (4, 0, 0), (4, 1, 1)]
     ref = O.saim(prob, par, 2, nthreads=NTHREADS)
     prog = ref["program"]
     for wpb, res, split in layouts:
