@@ -213,3 +213,41 @@ def test_every_tiling_is_bit_identical(need_gpu, case):
             out["lq"] = lam
             assert_round_equal(prog, ref["rounds"][k], out, k)
         inst.close()
+
+
+def test_degenerate_shapes(need_gpu):
+    """One item; one replica; one sweep; a zero capacity (no slack bits) next to
+    a constraint no item fits; an item heavier than the capacity; zero profits."""
+    one = G.Problem(G.KIND_QKP, np.array([[7]]), np.array([[3]]), np.array([5]), Fraction(1))
+    run_parity(one, G.Params(replicas=1, sweeps=3, beta=Fraction(4), eta=Fraction(2)), 3, label="QKP n=1 R=1")
+    run_parity(G.family0(4), G.Params(replicas=65, sweeps=1, beta=Fraction(2)), 2, label="QKP T=1")
+    rng = G.rng_for(960, 7)
+    a = rng.integers(1, 1000, size=(4, 50))
+    # b=0: no slack bits; b=1: a single slack bit; the last constraint holds every item
+    b = np.array([0, a[1].sum() // 4, 1, a[3].sum()])
+    prob = G.Problem(G.KIND_MKP, rng.integers(1, 500, size=50), a, b, Fraction(0))
+    par = G.Params(replicas=70, sweeps=30, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
+    assert B.pbit_plan(prob, par).n_ext == 50 + 0 + int(b[1]).bit_length() + 1 + int(b[3]).bit_length()
+    run_parity(prob, par, 3, label="MKP zero and tiny capacities")
+    zero = G.Problem(G.KIND_MKP, np.zeros(40, dtype=np.int64), rng.integers(1, 100, size=(2, 40)),
+                     np.array([500, 700]), Fraction(0))
+    run_parity(zero, par, 2, label="MKP zero profits")
+
+
+def test_maximum_shapes(need_gpu):
+    """The largest quadratic block count (N_ext up to 352) and the largest linear
+    shape: 32 constraints over close to the 2048-spin limit, whose per-site
+    constants do not fit LDS (the global-memory linear kernel), on sampled
+    replicas of round 0."""
+    q = G.qkp(336, Fraction(1, 2), G.rng_for(961, 0))
+    info = B.pbit_plan(q, G.Params())
+    assert info.n_pad == 352, info.n_pad
+    run_parity(q, G.Params(replicas=64, sweeps=8, beta=Fraction(5), eta=Fraction(20)), 2, label="QKP NB=11")
+    m32 = G.mkp(120, 32, G.rng_for(961, 1))
+    run_parity(m32, G.Params(replicas=64, sweeps=6, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5)), 2,
+               label="MKP M=32")
+    big = G.mkp(1400, 32, G.rng_for(961, 2))
+    par = G.Params(replicas=128, sweeps=3, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
+    assert 1900 < B.pbit_plan(big, par).n_ext <= 2048
+    say("[parity] MKP n=1400 M=32, sampled replicas")
+    _spot_check_round0(big, par, [0, 77, 127])
