@@ -503,7 +503,7 @@ const size_t kMaxLds = 160 * 1024;
 // LDS of the producer/consumer linear kernel.
 size_t linear_split_bytes(const Plan &P)
 {
-    return (size_t)kThetaBytes + kCoarseBytes + kRingBytes + (size_t)(32 * P.words + 32) * 16 +
+    return (size_t)kThetaBytes + kRingBytes + (size_t)(32 * P.words + 32) * 16 +
            (size_t)P.owords * 32 * P.m * 4 + (size_t)P.words * kWave * 4;
 }
 

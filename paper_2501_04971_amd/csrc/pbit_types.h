@@ -14,11 +14,7 @@ constexpr int kMaxWords = 64;               // linear kernel: n_ext <= 2048
 constexpr int kWave = 64;
 constexpr int kSnapshotBytes = 160;  // per-member record of batch snapshots
 constexpr int kBatchSplit = 0x100;   // work-item code flag: split (1 + 3 waves, 64 replicas) linear tile
-// producer/consumer kernels: coarse inverse of the threshold table (u24 in
-// buckets of 2^12) and the double-buffered threshold ring (32 sites x 64 lanes)
-constexpr int kCoarseBits = 12;
-constexpr int kCoarseLen = (1 << (24 - kCoarseBits)) + 1;
-constexpr size_t kCoarseBytes = ((size_t)kCoarseLen * 2 + 15) & ~(size_t)15;
+// producer/consumer kernels: double-buffered threshold ring (32 sites x 64 lanes)
 constexpr size_t kRingBytes = 2 * 32 * 64 * 8;
 
 // Everything a kernel needs about one instance; passed by value.

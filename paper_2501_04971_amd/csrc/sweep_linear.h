@@ -119,7 +119,10 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
         const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
         // original items, 32 per word of state
         for (int blk = 0; blk < d.owords; ++blk) {
-            uint32_t xw = xl[blk * kWave + lane];
+            // a site changes only at its own visit: old states are read from this
+            // copy, which keeps each record load off the chain of decisions
+            const uint32_t xw0 = xl[blk * kWave + lane];
+            uint32_t xw = xw0;
             const int64_t *rec = site + 4 * (blk * 32);
             const int32_t *ac0 = acol + (int64_t)(blk * 32) * M;
             uint32_t rnd[4] = {0u, 0u, 0u, 0u};
@@ -131,11 +134,11 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
             }
 #pragma unroll
             for (int s = 0; s < 32; ++s) {
-                const uint32_t xo = (xw >> s) & 1u;
+                const uint32_t xo = (xw0 >> s) & 1u;
                 uint32_t nA = 0u, nB = 0u;
                 if (s < 31) {
                     const int64_t *nx = rec + 4 * (s + 1);
-                    const uint32_t xo1 = (xw >> (s + 1)) & 1u;
+                    const uint32_t xo1 = (xw0 >> (s + 1)) & 1u;
                     const int64_t Z0 = (xo1 ? nx[1] : nx[0]) -
                                        constraint_field<M, WIDE>(ac0 + (s + 1) * M, g, k2);
                     const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
@@ -175,12 +178,13 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
                     thA = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
                     thB = thA;
                 }
+                const uint32_t sk0 = sk[k];
                 for (int q = 0; q < Qk; ++q) {
                     const int i = off + q;
-                    const uint32_t xo = (sk[k] >> q) & 1u;
+                    const uint32_t xo = (sk0 >> q) & 1u;
                     // both thresholds of bit q+1 (the record past the last bit is padding)
                     const int64_t *nx = site + 4 * (i + 1);
-                    const uint32_t xo1 = (sk[k] >> (q + 1)) & 1u;
+                    const uint32_t xo1 = (sk0 >> (q + 1)) & 1u;
                     const int64_t Z0 = (xo1 ? nx[1] : nx[0]) - ((int64_t)g[k] * k2) * ((int64_t)2 << q);
                     const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
                     const uint32_t nA = (uint32_t)th[theta_index(Z0, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
@@ -295,7 +299,10 @@ __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, 
         const int32_t Bt = d.Btab[t];
         const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
         for (int blk = 0; blk < owords; ++blk) {
-            uint32_t xw = xl[blk * kWave + lane];
+            // a site changes only at its own visit: old states are read from this
+            // copy, which keeps each record load off the chain of decisions
+            const uint32_t xw0 = xl[blk * kWave + lane];
+            uint32_t xw = xw0;
             const int rem = n - blk * 32;  // original items in this word (the rest are not visited here)
             uint32_t rnd[4];
 #pragma unroll
@@ -303,7 +310,7 @@ __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, 
                 const int i = blk * 32 + s;
                 if ((s & 3) == 0)
                     philox_block(cbase + (uint32_t)(i >> 2), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
-                const uint32_t xo = (xw >> s) & 1u;
+                const uint32_t xo = (xw0 >> s) & 1u;
                 const int32_t *a = ac + i * M;
                 const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
                 const int64_t dd = residual_dot<M, WIDE>(a, g);
@@ -325,13 +332,14 @@ __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, 
         for (int k = 0; k < M; ++k) {
             const int off = d.slack_off[k];
             const int Qk = d.slack_q[k];
+            const uint32_t sk0 = sk[k];
             for (int q = 0; q < Qk; ++q) {
                 const int i = off + q;
                 if ((i >> 2) != grp) {
                     grp = i >> 2;
                     philox_block(cbase + (uint32_t)grp, kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
                 }
-                const uint32_t xo = (sk[k] >> q) & 1u;
+                const uint32_t xo = (sk0 >> q) & 1u;
                 const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
                 const int64_t Z = K + (((int64_t)g[k] * negk2) << q);
                 const uint32_t thr = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];

@@ -17,7 +17,7 @@ namespace pbit {
 // (the host mirrors this in api.cpp, linear_split_bytes)
 inline size_t linear_pc_lds_bytes(int words, int owords, int m)
 {
-    return (size_t)kThetaBytes + kCoarseBytes + kRingBytes + (size_t)(32 * words + 32) * 16 +
+    return (size_t)kThetaBytes + kRingBytes + (size_t)(32 * words + 32) * 16 +
            (size_t)owords * 32 * m * 4 + (size_t)words * kWave * 4;
 }
 
@@ -27,11 +27,10 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
     const int words = d.words, owords = d.owords;
     const int n_rec = 32 * words + 32;
     int32_t *th = reinterpret_cast<int32_t *>(smem);
-    uint16_t *coarse = reinterpret_cast<uint16_t *>(smem + kThetaBytes);
-    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes + kCoarseBytes);
-    int64_t *kr = reinterpret_cast<int64_t *>(smem + kThetaBytes + kCoarseBytes + kRingBytes);
-    int32_t *ac = reinterpret_cast<int32_t *>(smem + kThetaBytes + kCoarseBytes + kRingBytes + (size_t)n_rec * 16);
-    uint32_t *xl = reinterpret_cast<uint32_t *>(smem + kThetaBytes + kCoarseBytes + kRingBytes +
+    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes);
+    int64_t *kr = reinterpret_cast<int64_t *>(smem + kThetaBytes + kRingBytes);
+    int32_t *ac = reinterpret_cast<int32_t *>(smem + kThetaBytes + kRingBytes + (size_t)n_rec * 16);
+    uint32_t *xl = reinterpret_cast<uint32_t *>(smem + kThetaBytes + kRingBytes +
                                                 (size_t)n_rec * 16 + (size_t)owords * 32 * M * 4);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -44,15 +43,13 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
     for (int e = threadIdx.x; e < owords * 32 * M; e += blockDim.x) ac[e] = d.acol[e];
     for (int e = threadIdx.x; e < words * kWave; e += blockDim.x) xl[e] = 0u;
     __syncthreads();
-    build_coarse(th, coarse);
-    __syncthreads();
 
     const int r = rbase + lane;  // every wave serves the same 64 replicas
     const uint32_t kround = (uint32_t)d.round_k[0];
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int total = d.T * words;  // ring blocks per run
 
-    if (wave > 0) produce_thresholds(d, wave - 1, 0, 0, ring, th, coarse, kround, m2);
+    if (wave > 0) produce_thresholds(d, wave - 1, 0, 0, ring, th, kround, m2);
     __syncthreads();
 
     // Every wave walks the same sequence of ring blocks and meets the others
@@ -75,13 +72,15 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
             const int base = w * 32;
             if (w < owords) {
                 // original items of this word (the tail beyond n is slack, visited below)
-                uint32_t xw = xl[w * kWave + lane];
+                // old states from the word's start (a site changes only at its own visit)
+                const uint32_t xw0 = xl[w * kWave + lane];
+                uint32_t xw = xw0;
                 const int rem = n - base;
 #pragma unroll
                 for (int s = 0; s < 32; ++s) {
                     const int i = base + s;
                     const int64_t hthr = rg[s * 64 + lane];
-                    const uint32_t xo = (xw >> s) & 1u;
+                    const uint32_t xo = (xw0 >> s) & 1u;
                     const int32_t *a = ac + i * M;
                     const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
                     const int64_t dd = residual_dot<M, WIDE>(a, g);
@@ -102,10 +101,11 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
                 for (int k = 0; k < M; ++k) {
                     const int off = d.slack_off[k];
                     const int q0 = max(0, lo - off), q1 = min(d.slack_q[k], hi - off);
+                    const uint32_t sk0 = sk[k];
                     for (int q = q0; q < q1; ++q) {
                         const int i = off + q;
                         const int64_t hthr = rg[(i - base) * 64 + lane];
-                        const uint32_t xo = (sk[k] >> q) & 1u;
+                        const uint32_t xo = (sk0 >> q) & 1u;
                         const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
                         const int64_t Z = K + (((int64_t)g[k] * negk2) << q);
                         const uint32_t xn = field_hi(Z, Bt, 0) >= hthr ? 1u : 0u;
@@ -116,7 +116,7 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
             }
         } else if (c + 1 < total) {
             const int t1 = (c + 1) / words, b1 = (c + 1) - t1 * words;
-            produce_thresholds(d, wave - 1, t1, b1, ring + (buf ^ 1) * 32 * 64, th, coarse, kround, m2);
+            produce_thresholds(d, wave - 1, t1, b1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
         }
         buf ^= 1;
         __syncthreads();

@@ -147,10 +147,12 @@ __device__ __forceinline__ void stream_slab(BlockVisit &v)
 }
 
 template <int s, int LS, int WPB>
-__device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8])
+__device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8])
 {
     stream_slab<s, (LS - 16) / 32, WPB>(v);
-    const uint32_t xo = (xc[s >> 2] >> (8 * (s & 3))) & 1u;
+    // old states come from the block-start copy (site s changes only at its own
+    // visit), which keeps the record loads off the chain of decisions
+    const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
     uint32_t nA = 0u, nB = 0u;
     if constexpr (s < 31) {
         const int64_t *nx = v.rec + 4 * (s + 1);
@@ -158,7 +160,7 @@ __device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8])
         const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + (s + 1) * LS);
 #pragma unroll
         for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
-        const uint32_t xo1 = (xc[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 1u;
+        const uint32_t xo1 = (x0[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 1u;
         const int64_t Z0 = (xo1 ? nx[1] : nx[0]) + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)nx[3], v.g) * v.k2;
         const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
         nA = (uint32_t)v.th[theta_index(Z0, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
@@ -183,10 +185,10 @@ __device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8])
 // One visit of site s without lookahead: its threshold is computed from the
 // current state right before the decision.
 template <int s, int LS, int WPB>
-__device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[8])
+__device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8])
 {
     stream_slab<s, (LS - 16) / 32, WPB>(v);
-    const uint32_t xo = (xc[s >> 2] >> (8 * (s & 3))) & 1u;
+    const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
     const int64_t *cur = v.rec + 4 * s;
     int32_t f = v.F[s];
     const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + s * LS);
@@ -223,10 +225,11 @@ __device__ __forceinline__ void visit_fence()
 template <int LS, int WPB, bool LA, int... S>
 __device__ __forceinline__ void visit_block(BlockVisit &v, uint32_t (&xc)[8], std::integer_sequence<int, S...>)
 {
+    const uint32_t x0[8] = {xc[0], xc[1], xc[2], xc[3], xc[4], xc[5], xc[6], xc[7]};
     if constexpr (LA)
-        ((visit_site<S, LS, WPB>(v, xc), visit_fence<S>()), ...);
+        ((visit_site<S, LS, WPB>(v, xc, x0), visit_fence<S>()), ...);
     else
-        ((visit_site_direct<S, LS, WPB>(v, xc), visit_fence<S>()), ...);
+        ((visit_site_direct<S, LS, WPB>(v, xc, x0), visit_fence<S>()), ...);
 }
 
 // One annealing run (T sweeps) of the replicas rbase + [0, 64 WPB) of instance

@@ -27,29 +27,17 @@ namespace pbit {
 template <int NB>
 constexpr size_t quad_pc_lds_bytes()
 {
-    return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 2 * (size_t)1024 * (NB + 1) + kCoarseBytes + kRingBytes;
-}
-
-// Largest array position p with th[p] <= u (th[0] = 0 <= u), by bisection.
-__device__ __forceinline__ int theta_floor_full(const int32_t *th, uint32_t u)
-{
-    int lo = 0, hi = kThetaLen - 1;
-#pragma unroll
-    for (int it = 0; it < 13; ++it) {
-        const int mid = (lo + hi + 1) >> 1;
-        const bool le = (uint32_t)th[mid] <= u;
-        const bool open = lo < hi;
-        lo = open && le ? mid : lo;
-        hi = open && !le ? mid - 1 : hi;
-    }
-    return lo;
+    return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 2 * (size_t)1024 * (NB + 1) + kRingBytes;
 }
 
 // Consumer visit of site s: thresholds come from the ring.
 template <int s, int LS>
-__device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], const int64_t *ring)
+__device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8],
+                                              const int64_t *ring)
 {
-    const uint32_t xo = (xc[s >> 2] >> (8 * (s & 3))) & 1u;
+    // site s changes only at its own visit, so its old state is read from the
+    // block-start copy: the record load below then waits on no earlier decision
+    const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
     const int64_t *cur = v.rec + 4 * s;
     const int64_t hthr = ring[s * 64 + (threadIdx.x & 63)];
     int32_t f = v.F[s];
@@ -70,7 +58,8 @@ template <int LS, int... S>
 __device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&xc)[8], const int64_t *ring,
                                                std::integer_sequence<int, S...>)
 {
-    ((visit_site_pc<S, LS>(v, xc, ring), visit_fence<S>()), ...);
+    const uint32_t x0[8] = {xc[0], xc[1], xc[2], xc[3], xc[4], xc[5], xc[6], xc[7]};
+    ((visit_site_pc<S, LS>(v, xc, x0, ring), visit_fence<S>()), ...);
 }
 
 // Guess of the largest table position p with th[p] <= u from the inverse of
@@ -85,43 +74,46 @@ __device__ __forceinline__ int theta_floor_guess(uint32_t u)
 }
 
 // Producer p (0..2) fills the ring buffer of block blk (sites 32 blk ..
-// 32 blk + 31) of sweep t: Philox groups g = p, p + 3, p + 6 (four sites each;
-// producer 2 has two groups).  The table position of each draw comes from
-// theta_floor_guess, accepted only where the table confirms it; the rest (flat
-// tails, where many positions share a value) is settled by an exact bisection
-// between the coarse table's bounds.  Sites at or beyond N_ext never flip.
+// 32 blk + 31) of sweep t: Philox groups g = p, p + 3, p + 6 (four sites each).
+// Producer 2 has only two groups; it computes a third and discards it, so that
+// all three run the same code with no branch between the twelve table searches
+// and the scheduler can overlap them.  The table position of each draw comes
+// from theta_floor_guess, accepted only where the table confirms it; the rest
+// (flat tails, where many positions share a value: a few draws in 10^6) is
+// settled by an exact bisection over the whole table.  Sites at or beyond
+// N_ext never flip.
 __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, int t, int blk, int64_t *ring,
-                                                   const int32_t *th, const uint16_t *coarse, uint32_t kround,
-                                                   uint64_t m2)
+                                                   const int32_t *th, uint32_t kround, uint64_t m2)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
-    const bool third = p + 6 < 8;
     uint32_t u[12];
-    int lo[12], hi[12];
+    int gs[12];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        uint32_t rnd[4] = {0u, 0u, 0u, 0u};
-        if (k < 2 || third)
-            philox_block(cbase + (uint32_t)(blk * 8 + p + 3 * k), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
+        uint32_t rnd[4];
+        philox_block(cbase + (uint32_t)(blk * 8 + p + 3 * k), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int e = 4 * k + q;
-            u[e] = rnd[q] >> 8;
-            // fast path: invert the table's generating function and check the
-            // guess and its neighbours against the table itself
-            const int g = theta_floor_guess(u[e]);
-            const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
-                           t3 = (uint32_t)th[g + 2];
-            const bool c0 = t0 <= u[e] && u[e] < t1, c1 = t1 <= u[e] && u[e] < t2, c2 = t2 <= u[e] && u[e] < t3;
-            const int found = c1 ? g : (c0 ? g - 1 : g + 1);
-            const bool ok = c0 || c1 || c2 || !(k < 2 || third);
-            const int b = (int)(u[e] >> kCoarseBits);
-            lo[e] = ok ? found : (int)coarse[b];
-            hi[e] = ok ? found : (int)coarse[b + 1];
+            u[4 * k + q] = rnd[q] >> 8;
+            gs[4 * k + q] = theta_floor_guess(u[4 * k + q]);
         }
     }
-    // exact bisection for the draws the fast path did not settle
+    int lo[12], hi[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        // fast path: check the guess and its neighbours against the table itself
+        const int g = gs[e];
+        const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
+                       t3 = (uint32_t)th[g + 2];
+        const bool c0 = t0 <= u[e] && u[e] < t1, c1 = t1 <= u[e] && u[e] < t2, c2 = t2 <= u[e] && u[e] < t3;
+        const int found = c1 ? g : (c0 ? g - 1 : g + 1);
+        const bool ok = c0 || c1 || c2 || p + 3 * (e >> 2) >= 8;  // (a discarded group needs no search)
+        lo[e] = ok ? found : 0;
+        hi[e] = ok ? found : kThetaLen - 1;
+    }
+    // exact bisection for the draws the fast path did not settle: th[lo] <= u
+    // holds throughout (th[0] = 0), and the search ends at the largest such lo
     for (;;) {
         bool any = false;
 #pragma unroll
@@ -139,7 +131,7 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (k < 2 || third) {
+        if (p + 3 * k < 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int s = 4 * (p + 3 * k) + q;
@@ -150,28 +142,33 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
     }
 }
 
-// Producer p's share of the next J slab (quadratic kernel).
+// Producer p's share of the next J slab (quadratic kernel): loaded into
+// registers before the producer's other work of the block and stored after
+// it, so that the global loads' latency is hidden.
 template <int NB>
-__device__ __forceinline__ void produce_slab(int p, const int8_t *jsrc, int8_t *ldst)
+constexpr int slab_pieces_per_producer()
+{
+    return (NB + 1 + 2) / 3;
+}
+
+template <int NB>
+__device__ __forceinline__ void load_slab(int p, const int8_t *jsrc, uint4 (&pf)[slab_pieces_per_producer<NB>()])
 {
     constexpr int PIECES = NB + 1;
     const int lane = threadIdx.x & 63;
-    uint4 pf[(PIECES + 2) / 3];
 #pragma unroll
-    for (int j = 0; j < (PIECES + 2) / 3; ++j)
+    for (int j = 0; j < slab_pieces_per_producer<NB>(); ++j)
         pf[j] = *reinterpret_cast<const uint4 *>(jsrc + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16);
-#pragma unroll
-    for (int j = 0; j < (PIECES + 2) / 3; ++j)
-        *reinterpret_cast<uint4 *>(ldst + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16) = pf[j];
 }
 
-// Builds the coarse table of theta_floor at the bucket edges (whole workgroup).
-__device__ __forceinline__ void build_coarse(const int32_t *th, uint16_t *coarse)
+template <int NB>
+__device__ __forceinline__ void store_slab(int p, int8_t *ldst, const uint4 (&pf)[slab_pieces_per_producer<NB>()])
 {
-    for (int b = threadIdx.x; b < kCoarseLen; b += blockDim.x) {
-        const uint32_t u = min((uint32_t)b << kCoarseBits, (1u << 24) - 1u);
-        coarse[b] = (uint16_t)theta_floor_full(th, u);
-    }
+    constexpr int PIECES = NB + 1;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < slab_pieces_per_producer<NB>(); ++j)
+        *reinterpret_cast<uint4 *>(ldst + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16) = pf[j];
 }
 
 // One annealing run of replicas rbase + [0, 64) by a workgroup of 4 waves
@@ -186,8 +183,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     int32_t *th = reinterpret_cast<int32_t *>(smem);
     int64_t *site = reinterpret_cast<int64_t *>(smem + kThetaBytes);
     int8_t *slabs = reinterpret_cast<int8_t *>(smem + kThetaBytes + NP * 32);
-    uint16_t *coarse = reinterpret_cast<uint16_t *>(smem + kThetaBytes + NP * 32 + 2 * SLAB);
-    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes + NP * 32 + 2 * SLAB + kCoarseBytes);
+    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes + NP * 32 + 2 * SLAB);
 
     copy_slab<NB>(d.J, 0, slabs);
     for (int e = threadIdx.x; e < kThetaLen; e += blockDim.x) th[e] = d.theta[e];
@@ -197,8 +193,6 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
         for (int e = threadIdx.x; e < NP * 2; e += blockDim.x) dst[e] = src[e];
     }
     __syncthreads();
-    build_coarse(th, coarse);
-    __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -207,7 +201,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int total = d.T * NB;
 
-    if (wave > 0) produce_thresholds(d, wave - 1, 0, 0, ring, th, coarse, kround, m2);
+    if (wave > 0) produce_thresholds(d, wave - 1, 0, 0, ring, th, kround, m2);
     __syncthreads();
 
     uint32_t x[NB][8];
@@ -255,8 +249,10 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             // the next block's thresholds and slab (after the last block: slab 0
             // for the scoring pass, no thresholds)
             const int t1 = (c + 1) / NB, blk1 = (c + 1) - t1 * NB;
-            if (c + 1 < total) produce_thresholds(d, wave - 1, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, coarse, kround, m2);
-            produce_slab<NB>(wave - 1, d.J + (size_t)blk1 * SLAB, slabs + (buf ^ 1) * SLAB);
+            uint4 pf[slab_pieces_per_producer<NB>()];
+            load_slab<NB>(wave - 1, d.J + (size_t)blk1 * SLAB, pf);
+            if (c + 1 < total) produce_thresholds(d, wave - 1, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
+            store_slab<NB>(wave - 1, slabs + (buf ^ 1) * SLAB, pf);
         }
         buf ^= 1;
         __syncthreads();

@@ -3,6 +3,8 @@
 
 namespace pbit {
 
+static_assert(quad_pc_lds_bytes<kMaxQuadBlocks>() <= 160 * 1024, "split layout exceeds the LDS of a CU");
+
 template <int NB>
 __global__ __launch_bounds__(256) void sweep_quad_pc(const DevInstance d)
 {
