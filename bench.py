@@ -44,7 +44,7 @@ LDS_PEAK = 256 * 128 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2)
 # and WRITE_SIZE (x1) passes (calibrated on a 256 MiB copy); valid for the
 # kernel build they were taken on, keyed by kernel and workload.
-MEASURED_TRAFFIC = {("sweep_quad_pc<10>", 2): (886 * 2 + 224) * 1024}
+MEASURED_TRAFFIC = {}
 
 WORKLOAD_NAMES = {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10", 2: "QKP N=300 d=1.0",
                   3: "mixed batch: 256 QKP + 256 MKP, 256 replicas each"}
@@ -52,6 +52,13 @@ WORKLOAD_NAMES = {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10", 2: "QKP N=300 d=1.
 
 def alu_ops_per_update(m: int) -> int:
     return ALU_OPS_RNG + ALU_OPS_FIXED + 2 * m
+
+
+def linear_split_lds(info, n):
+    """LDS bytes of the split linear kernel (threshold table, ring, per-site
+    constants, coefficient columns, state words)."""
+    owords = (n + 31) // 32
+    return 18448 + 2 * 32 * 64 * 8 + (32 * info.words + 32) * 16 + owords * 32 * info.m * 4 + info.words * 64 * 4
 
 
 def quad_secondary(info, updates, seconds):
@@ -203,13 +210,17 @@ def main() -> int:
                "sweeps_per_round": "QKP 1000, MKP 2000", "updates_per_step": updates_per_step,
                "parallelism": "one GPU, persistent work queue over (instance, 256-replica tile)"}
     else:
+        # the layout pbit_sample_round picks by default: the split form whenever
+        # one wave per 64 replicas leaves CUs idle and (linear kernel) its LDS fits
         groups = (par.replicas + 63) // 64
-        split = info.variant == 0 and groups <= torch.cuda.get_device_properties(0).multi_processor_count
+        fits = info.variant == 0 or linear_split_lds(info, prob.n) <= 160 * 1024
+        split = groups <= torch.cuda.get_device_properties(0).multi_processor_count and fits
         waves = 4 * groups if split else groups
         best = runner.best_feasible()
         nb = info.n_pad // 32
+        wide = "true" if info.variant == 2 else "false"
         kernel = (f"sweep_quad_pc<{nb}>" if split else f"sweep_quad<{nb}>") if info.variant == 0 else \
-            f"sweep_linear<{info.m}>"
+            (f"sweep_linear_pc<{info.m}, {wide}>" if split else f"sweep_linear<{info.m}, {wide}, ...>")
         secondary = quad_secondary(info, updates_per_step, launch_ms / 1e3) if info.variant == 0 else {}
         cfg = {"workload": WORKLOAD_NAMES[args.workload], "n_ext": info.n_ext, "constraints": info.m,
                "replicas": par.replicas, "sweeps_per_round": par.sweeps,

@@ -103,12 +103,14 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
 #pragma unroll
     for (int e = 0; e < 12; ++e) {
         // fast path: check the guess and its neighbours against the table itself
+        // (th is non-decreasing: within th[g - 1] <= u < th[g + 2] the position
+        // is g - 1 plus the number of th[g], th[g + 1] that are <= u; bitwise
+        // operators, so that all four entries are read unconditionally)
         const int g = gs[e];
         const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
                        t3 = (uint32_t)th[g + 2];
-        const bool c0 = t0 <= u[e] && u[e] < t1, c1 = t1 <= u[e] && u[e] < t2, c2 = t2 <= u[e] && u[e] < t3;
-        const int found = c1 ? g : (c0 ? g - 1 : g + 1);
-        const bool ok = c0 || c1 || c2 || p + 3 * (e >> 2) >= 8;  // (a discarded group needs no search)
+        const int found = g - 1 + (int)(t1 <= u[e]) + (int)(t2 <= u[e]);
+        const bool ok = ((t0 <= u[e]) & (u[e] < t3)) | (p + 3 * (e >> 2) >= 8);  // (a discarded group needs no search)
         lo[e] = ok ? found : 0;
         hi[e] = ok ? found : kThetaLen - 1;
     }
@@ -129,13 +131,17 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
             }
         }
     }
+    // thresholds j* 2^ish - irnd; |j*| < 2^12, so without saturation whenever
+    // ish <= 50 (the common case, uniform per instance)
+    const bool nosat = d.ish <= 50;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (p + 3 * k < 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int s = 4 * (p + 3 * k) + q;
-                const int64_t h = index_threshold(lo[4 * k + q] + 1 - kThetaHalf, d.ish) - d.irnd;
+                const int js = lo[4 * k + q] + 1 - kThetaHalf;
+                const int64_t h = (nosat ? (int64_t)js * ((int64_t)1 << d.ish) : index_threshold(js, d.ish)) - d.irnd;
                 ring[s * 64 + lane] = blk * 32 + s < d.n_ext ? h : INT64_MAX;
             }
         }
