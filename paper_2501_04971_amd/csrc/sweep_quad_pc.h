@@ -201,7 +201,9 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave-uniform by construction; saying so lets the compiler split consumer
+    // and producers with scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int r = rbase + lane;  // every wave serves the same 64 replicas
     const uint32_t kround = (uint32_t)d.round_k[0];
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
