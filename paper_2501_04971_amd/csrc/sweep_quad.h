@@ -38,6 +38,19 @@
 
 namespace pbit {
 
+// Accumulators of the two 32-replica halves (row 8(v/4) + 4(lane/32) + v%4,
+// column lane%32) -> owner layout (lane r holds the 32 fields of replica r).
+__device__ __forceinline__ void fields_from_acc(const v16i &acc0, const v16i &acc1, int32_t (&F)[32])
+{
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        uint32_t lo = (uint32_t)acc0[v], hi = (uint32_t)acc1[v];
+        swap_halves(lo, hi);
+        F[8 * (v >> 2) + (v & 3)] = (int32_t)lo;
+        F[8 * (v >> 2) + 4 + (v & 3)] = (int32_t)hi;
+    }
+}
+
 // Block fields F[blk*32 + s] = sum_j W[blk*32+s, j] x_j for the 64 replicas of
 // the wave; slab holds rows blk*32..blk*32+31 of W.
 template <int NB>
@@ -59,14 +72,7 @@ __device__ __forceinline__ void block_fields(const int8_t *slab, int blk, const 
         acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B0, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B1, acc1, 0, 0, 0);
     }
-    // accumulator row 8(v/4) + 4(lane/32) + v%4, column lane%32 -> owner layout
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        uint32_t lo = (uint32_t)acc0[v], hi = (uint32_t)acc1[v];
-        swap_halves(lo, hi);
-        F[8 * (v >> 2) + (v & 3)] = (int32_t)lo;
-        F[8 * (v >> 2) + 4 + (v & 3)] = (int32_t)hi;
-    }
+    fields_from_acc(acc0, acc1, F);
 }
 
 template <int NB>

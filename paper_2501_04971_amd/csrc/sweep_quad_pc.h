@@ -27,7 +27,7 @@ namespace pbit {
 template <int NB>
 constexpr size_t quad_pc_lds_bytes()
 {
-    return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 2 * (size_t)1024 * (NB + 1) + kRingBytes;
+    return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 3 * (size_t)1024 * (NB + 1) + kRingBytes;
 }
 
 // Consumer visit of site s: thresholds come from the ring.
@@ -54,12 +54,41 @@ __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], 
     v.g += __mul24(delta, (int32_t)meta);
 }
 
-template <int LS, int... S>
-__device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&xc)[8], const int64_t *ring,
-                                               std::integer_sequence<int, S...>)
+// Fields of the next block, accumulated on the matrix cores while the current
+// block is visited.  With the state rotated so that x[0] is the current block
+// b, the next block's field is W[b+1, :] . x = sum over chunks p = 1 .. NB-1 of
+// W[b+1, chunk (b+p)] . x[p] (unchanged by this block's visits) plus
+// W[b+1, chunk b] . x[0], added once the visits are done.  The partial products
+// are spread over the visits (one MFMA pair every STEP visits), so their
+// latency overlaps the visit chain instead of adding to it.
+struct NextFields {
+    v16i acc0, acc1;
+    const int8_t *arow;  // LDS: this lane's A-operand row of the next block's slab
+    int cbase;           // x[p] holds block (cbase + p - 1) mod NB, cbase = b + 1
+};
+
+template <int s, int NB>
+__device__ __forceinline__ void next_fields_step(NextFields &nf, const uint32_t (&x)[NB][8])
 {
-    const uint32_t x0[8] = {xc[0], xc[1], xc[2], xc[3], xc[4], xc[5], xc[6], xc[7]};
-    ((visit_site_pc<S, LS>(v, xc, x0, ring), visit_fence<S>()), ...);
+    constexpr int STEP = NB > 1 ? 32 / (NB - 1) : 33;
+    if constexpr (NB > 1 && s % STEP == 0 && s / STEP < NB - 1) {
+        constexpr int p = s / STEP + 1;
+        int c = nf.cbase + p - 1;
+        c = c >= NB ? c - NB : c;
+        const v4i A = *reinterpret_cast<const v4i *>(nf.arow + c * 32);
+        const v4i B0 = {(int)x[p][0], (int)x[p][1], (int)x[p][2], (int)x[p][3]};
+        const v4i B1 = {(int)x[p][4], (int)x[p][5], (int)x[p][6], (int)x[p][7]};
+        nf.acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B0, nf.acc0, 0, 0, 0);
+        nf.acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B1, nf.acc1, 0, 0, 0);
+    }
+}
+
+template <int LS, int NB, int... S>
+__device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&x)[NB][8], NextFields &nf,
+                                               const int64_t *ring, std::integer_sequence<int, S...>)
+{
+    const uint32_t x0[8] = {x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], x[0][5], x[0][6], x[0][7]};
+    ((visit_site_pc<S, LS>(v, x[0], x0, ring), next_fields_step<S, NB>(nf, x), visit_fence<S>()), ...);
 }
 
 // Guess of the largest table position p with th[p] <= u from the inverse of
@@ -188,10 +217,13 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     constexpr int SLAB = 1024 * (NB + 1);
     int32_t *th = reinterpret_cast<int32_t *>(smem);
     int64_t *site = reinterpret_cast<int64_t *>(smem + kThetaBytes);
-    int8_t *slabs = reinterpret_cast<int8_t *>(smem + kThetaBytes + NP * 32);
-    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes + NP * 32 + 2 * SLAB);
+    int8_t *slabs = reinterpret_cast<int8_t *>(smem + kThetaBytes + NP * 32);  // three buffers
+    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes + NP * 32 + 3 * SLAB);
 
+    // the slab of block step c (block c % NB) sits in buffer c % 3 during steps
+    // c - 1 (the next block's fields) and c (its in-block couplings)
     copy_slab<NB>(d.J, 0, slabs);
+    copy_slab<NB>(d.J, 1 % NB, slabs + SLAB);
     for (int e = threadIdx.x; e < kThetaLen; e += blockDim.x) th[e] = d.theta[e];
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(d.site);
@@ -235,13 +267,16 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     v.wave = wave;
     v.nw = 1;
 
-    int buf = 0;
+    if (wave == 0) block_fields<NB>(slabs, 0, x, v.F);  // fields of the first block
+
+    int buf = 0;         // ring buffer of block step c
+    int b0 = 0, b1 = 1;  // slab buffers of steps c and c + 1 (c % 3, (c + 1) % 3)
     for (int c = 0; c < total; ++c) {
         const int t = c / NB, blk = c - (c / NB) * NB;
+        const int b2 = b1 == 2 ? 0 : b1 + 1;
         if (wave == 0) {
-            const int8_t *slab = slabs + buf * SLAB;
+            const int8_t *slab = slabs + b0 * SLAB;
             v.Bt = d.Btab[t];
-            block_fields<NB>(slab, blk, x, v.F);
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             v.rec = site + 4 * (blk * 32);
@@ -249,20 +284,37 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             v.blk = blk;
 #pragma unroll
             for (int w = 0; w < 8; ++w) v.dx[w] = 0u;
-            visit_block_pc<LS>(v, x[0], ring + buf * 32 * 64, std::make_integer_sequence<int, 32>{});
+            NextFields nf;
+            nf.acc0 = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            nf.acc1 = nf.acc0;
+            nf.arow = slabs + b1 * SLAB + (lane & 31) * LS + (lane >> 5) * 16;
+            nf.cbase = blk + 1;
+            visit_block_pc<LS, NB>(v, x, nf, ring + buf * 32 * 64, std::make_integer_sequence<int, 32>{});
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
+            {
+                // this block's own chunk completes the next block's fields
+                const v4i A = *reinterpret_cast<const v4i *>(nf.arow + blk * 32);
+                const v4i B0 = {(int)x[0][0], (int)x[0][1], (int)x[0][2], (int)x[0][3]};
+                const v4i B1 = {(int)x[0][4], (int)x[0][5], (int)x[0][6], (int)x[0][7]};
+                nf.acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B0, nf.acc0, 0, 0, 0);
+                nf.acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B1, nf.acc1, 0, 0, 0);
+            }
             rotate_chunks<NB>(x);
+            fields_from_acc(nf.acc0, nf.acc1, v.F);
         } else {
-            // the next block's thresholds and slab (after the last block: slab 0
-            // for the scoring pass, no thresholds)
+            // the next block's thresholds, and the slab of the block after it
+            // (at the end: slabs 0 and 1 for the scoring pass, no thresholds)
             const int t1 = (c + 1) / NB, blk1 = (c + 1) - t1 * NB;
+            const int blk2 = (c + 2) % NB;
             uint4 pf[slab_pieces_per_producer<NB>()];
-            load_slab<NB>(wave - 1, d.J + (size_t)blk1 * SLAB, pf);
+            load_slab<NB>(wave - 1, d.J + (size_t)blk2 * SLAB, pf);
             if (c + 1 < total) produce_thresholds(d, wave - 1, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
-            store_slab<NB>(wave - 1, slabs + (buf ^ 1) * SLAB, pf);
+            store_slab<NB>(wave - 1, slabs + b2 * SLAB, pf);
         }
         buf ^= 1;
+        b0 = b1;
+        b1 = b2;
         __syncthreads();
     }
 
@@ -271,10 +323,10 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     const bool live = wave == 0 && r < d.R;
     int64_t pacc = 0;
     int32_t sval = 0;
-    // slab 0 is in buffer `buf` after the last block wrapped around
+    // slab 0 is in buffer b0 after the last block wrapped around (and slab 1 in b1)
     for (int blk = 0; blk < NB; ++blk) {
-        const int8_t *slab = slabs + buf * SLAB;
-        if (blk + 1 < NB) copy_slab<NB>(d.J, blk + 1, slabs + (buf ^ 1) * SLAB);
+        const int8_t *slab = slabs + b0 * SLAB;
+        if (blk + 1 < NB) copy_slab<NB>(d.J, blk + 1, slabs + b1 * SLAB);
         if (wave == 0) {
             int32_t F[32];
             block_fields<NB>(slab, blk, x, F);
@@ -299,7 +351,9 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             rotate_chunks<NB>(x);
         }
-        buf ^= 1;
+        const int bt = b0;
+        b0 = b1;
+        b1 = bt;
         __syncthreads();
     }
     if (live) {
