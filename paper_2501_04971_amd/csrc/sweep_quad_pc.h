@@ -46,7 +46,8 @@ __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], 
     for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
     const int64_t meta = cur[3];
     // v.k2 holds -k2 here; the ring holds the threshold less the rounding term
-    const int64_t Z = (xo ? cur[1] : cur[0]) + (int64_t)(f * 256) * v.sg2 + (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
+    // (the record holds K0, K1 in its first two words: indexed by the old state)
+    const int64_t Z = cur[xo] + (int64_t)(f * 256) * v.sg2 + (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
     const uint32_t xn = field_hi(Z, v.Bt, 0) >= hthr ? 1u : 0u;
     const int32_t delta = (int32_t)xn - (int32_t)xo;
     xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
