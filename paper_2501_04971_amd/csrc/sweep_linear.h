@@ -128,7 +128,7 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
             uint32_t rnd[4] = {0u, 0u, 0u, 0u};
             uint32_t thA, thB, pend = 0u;
             {
-                const int64_t Z = ((xw & 1u) ? rec[1] : rec[0]) - constraint_field<M, WIDE>(ac0, g, k2);
+                const int64_t Z = rec[xw & 1u] - constraint_field<M, WIDE>(ac0, g, k2);
                 thA = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
                 thB = thA;
             }
@@ -139,7 +139,7 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
                 if (s < 31) {
                     const int64_t *nx = rec + 4 * (s + 1);
                     const uint32_t xo1 = (xw0 >> (s + 1)) & 1u;
-                    const int64_t Z0 = (xo1 ? nx[1] : nx[0]) -
+                    const int64_t Z0 = nx[xo1] -
                                        constraint_field<M, WIDE>(ac0 + (s + 1) * M, g, k2);
                     const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
                     nA = (uint32_t)th[theta_index(Z0, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
@@ -174,7 +174,7 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
                 uint32_t thA, thB, pend = 0u;
                 {
                     const int64_t *rec = site + 4 * off;
-                    const int64_t Z = ((sk[k] & 1u) ? rec[1] : rec[0]) - (int64_t)g[k] * k2;
+                    const int64_t Z = rec[sk[k] & 1u] - (int64_t)g[k] * k2;
                     thA = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
                     thB = thA;
                 }
@@ -185,7 +185,7 @@ __device__ __forceinline__ void linear_run(const DevInstance &d, int rbase, unsi
                     // both thresholds of bit q+1 (the record past the last bit is padding)
                     const int64_t *nx = site + 4 * (i + 1);
                     const uint32_t xo1 = (sk0 >> (q + 1)) & 1u;
-                    const int64_t Z0 = (xo1 ? nx[1] : nx[0]) - ((int64_t)g[k] * k2) * ((int64_t)2 << q);
+                    const int64_t Z0 = nx[xo1] - ((int64_t)g[k] * k2) * ((int64_t)2 << q);
                     const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
                     const uint32_t nA = (uint32_t)th[theta_index(Z0, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
                     const uint32_t nB = (uint32_t)th[theta_index(Z1, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
@@ -312,7 +312,7 @@ __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, 
                     philox_block(cbase + (uint32_t)(i >> 2), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
                 const uint32_t xo = (xw0 >> s) & 1u;
                 const int32_t *a = ac + i * M;
-                const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
+                const int64_t K = kr[2 * i + xo];
                 const int64_t dd = residual_dot<M, WIDE>(a, g);
                 const int64_t Z = WIDE ? K + dd * (int64_t)negk2 : K + (int64_t)(int32_t)dd * negk2;
                 const uint32_t thr = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf] &
@@ -340,7 +340,7 @@ __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, 
                     philox_block(cbase + (uint32_t)grp, kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
                 }
                 const uint32_t xo = (sk0 >> q) & 1u;
-                const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
+                const int64_t K = kr[2 * i + xo];
                 const int64_t Z = K + (((int64_t)g[k] * negk2) << q);
                 const uint32_t thr = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf];
                 const int sel = i & 3;

@@ -82,7 +82,7 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
                     const int64_t hthr = rg[s * 64 + lane];
                     const uint32_t xo = (xw0 >> s) & 1u;
                     const int32_t *a = ac + i * M;
-                    const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
+                    const int64_t K = kr[2 * i + xo];
                     const int64_t dd = residual_dot<M, WIDE>(a, g);
                     const int64_t Z = WIDE ? K + dd * (int64_t)negk2 : K + (int64_t)(int32_t)dd * negk2;
                     // sites past the original items belong to the slack loop: never flip here
@@ -106,7 +106,7 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
                         const int i = off + q;
                         const int64_t hthr = rg[(i - base) * 64 + lane];
                         const uint32_t xo = (sk0 >> q) & 1u;
-                        const int64_t K = xo ? kr[2 * i + 1] : kr[2 * i];
+                        const int64_t K = kr[2 * i + xo];
                         const int64_t Z = K + (((int64_t)g[k] * negk2) << q);
                         const uint32_t xn = field_hi(Z, Bt, 0) >= hthr ? 1u : 0u;
                         g[k] += ((int32_t)xn - (int32_t)xo) << q;

@@ -167,7 +167,7 @@ __device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8], con
 #pragma unroll
         for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
         const uint32_t xo1 = (x0[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 1u;
-        const int64_t Z0 = (xo1 ? nx[1] : nx[0]) + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)nx[3], v.g) * v.k2;
+        const int64_t Z0 = nx[xo1] + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)nx[3], v.g) * v.k2;
         const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
         nA = (uint32_t)v.th[theta_index(Z0, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
         nB = (uint32_t)v.th[theta_index(Z1, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
@@ -201,7 +201,7 @@ __device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[
 #pragma unroll
     for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
     const int64_t meta = cur[3];
-    const int64_t Z = (xo ? cur[1] : cur[0]) + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
+    const int64_t Z = cur[xo] + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
     const uint32_t thr = (uint32_t)v.th[theta_index(Z, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf] &
                          (uint32_t)(meta >> 32);
     if constexpr ((s & 3) == 0)
@@ -315,7 +315,7 @@ __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsign
             // thresholds of site 0 (nothing pending at a block start)
             if constexpr (LA) {
                 const uint32_t xo0 = x[0][0] & 1u;
-                const int64_t Z = (xo0 ? v.rec[1] : v.rec[0]) + (int64_t)(v.F[0] * 256) * v.sg2 -
+                const int64_t Z = v.rec[xo0] + (int64_t)(v.F[0] * 256) * v.sg2 -
                                   (int64_t)__mul24((int32_t)v.rec[3], v.g) * v.k2;
                 v.thA = (uint32_t)th[theta_index(Z, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
                 v.thB = v.thA;
