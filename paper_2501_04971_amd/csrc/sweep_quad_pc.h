@@ -60,23 +60,35 @@ __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], 
 // b, the next block's field is W[b+1, :] . x = sum over chunks p = 1 .. NB-1 of
 // W[b+1, chunk (b+p)] . x[p] (unchanged by this block's visits) plus
 // W[b+1, chunk b] . x[0], added once the visits are done.  The partial products
-// are spread over the visits (one MFMA pair every STEP visits), so their
-// latency overlaps the visit chain instead of adding to it.
+// are spread over the visits (one MFMA pair every STEP visits, operands loaded
+// at the block start), so their latency overlaps the visit chain instead of
+// adding to it.
+template <int NB>
 struct NextFields {
     v16i acc0, acc1;
-    const int8_t *arow;  // LDS: this lane's A-operand row of the next block's slab
-    int cbase;           // x[p] holds block (cbase + p - 1) mod NB, cbase = b + 1
+    const int8_t *arow;             // LDS: this lane's A-operand row of the next block's slab
+    v4i a[NB > 1 ? NB - 1 : 1];     // A operands of chunks p = 1 .. NB-1, loaded at the block start
+
+    // x[p] holds block (b + p) mod NB, whose columns of the next block's rows
+    // are chunk (b + p) mod NB of the slab
+    __device__ __forceinline__ void load(int b)
+    {
+#pragma unroll
+        for (int p = 1; p < NB; ++p) {
+            int c = b + p;
+            c = c >= NB ? c - NB : c;
+            a[p - 1] = *reinterpret_cast<const v4i *>(arow + c * 32);
+        }
+    }
 };
 
 template <int s, int NB>
-__device__ __forceinline__ void next_fields_step(NextFields &nf, const uint32_t (&x)[NB][8])
+__device__ __forceinline__ void next_fields_step(NextFields<NB> &nf, const uint32_t (&x)[NB][8])
 {
     constexpr int STEP = NB > 1 ? 32 / (NB - 1) : 33;
     if constexpr (NB > 1 && s % STEP == 0 && s / STEP < NB - 1) {
         constexpr int p = s / STEP + 1;
-        int c = nf.cbase + p - 1;
-        c = c >= NB ? c - NB : c;
-        const v4i A = *reinterpret_cast<const v4i *>(nf.arow + c * 32);
+        const v4i A = nf.a[p - 1];
         const v4i B0 = {(int)x[p][0], (int)x[p][1], (int)x[p][2], (int)x[p][3]};
         const v4i B1 = {(int)x[p][4], (int)x[p][5], (int)x[p][6], (int)x[p][7]};
         nf.acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B0, nf.acc0, 0, 0, 0);
@@ -85,7 +97,7 @@ __device__ __forceinline__ void next_fields_step(NextFields &nf, const uint32_t 
 }
 
 template <int LS, int NB, int... S>
-__device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&x)[NB][8], NextFields &nf,
+__device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&x)[NB][8], NextFields<NB> &nf,
                                                const int64_t *ring, std::integer_sequence<int, S...>)
 {
     const uint32_t x0[8] = {x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], x[0][5], x[0][6], x[0][7]};
@@ -285,11 +297,11 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             v.blk = blk;
 #pragma unroll
             for (int w = 0; w < 8; ++w) v.dx[w] = 0u;
-            NextFields nf;
+            NextFields<NB> nf;
             nf.acc0 = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
             nf.acc1 = nf.acc0;
             nf.arow = slabs + b1 * SLAB + (lane & 31) * LS + (lane >> 5) * 16;
-            nf.cbase = blk + 1;
+            nf.load(blk);
             visit_block_pc<LS, NB>(v, x, nf, ring + buf * 32 * 64, std::make_integer_sequence<int, 32>{});
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
