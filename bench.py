@@ -215,11 +215,12 @@ def main() -> int:
         groups = (par.replicas + 63) // 64
         fits = info.variant == 0 or linear_split_lds(info, prob.n) <= 160 * 1024
         split = groups <= torch.cuda.get_device_properties(0).multi_processor_count and fits
-        waves = 4 * groups if split else groups
-        best = runner.best_feasible()
         nb = info.n_pad // 32
+        producers = 6 if info.variant == 0 and nb <= 4 else 3  # the library's default for the split form
+        waves = (8 if producers == 6 else 4) * groups if split else groups
+        best = runner.best_feasible()
         wide = "true" if info.variant == 2 else "false"
-        kernel = (f"sweep_quad_pc<{nb}>" if split else f"sweep_quad<{nb}>") if info.variant == 0 else \
+        kernel = (f"sweep_quad_pc<{nb}, {producers}>" if split else f"sweep_quad<{nb}>") if info.variant == 0 else \
             (f"sweep_linear_pc<{info.m}, {wide}>" if split else f"sweep_linear<{info.m}, {wide}, ...>")
         secondary = quad_secondary(info, updates_per_step, launch_ms / 1e3) if info.variant == 0 else {}
         cfg = {"workload": WORKLOAD_NAMES[args.workload], "n_ext": info.n_ext, "constraints": info.m,

@@ -7,7 +7,8 @@ purely a speed question, answered by measurement:
 * single instances: waves of 64 replicas per workgroup (quadratic kernel 1 or
   4; linear kernel 1..4), for the linear kernel whether the per-site
   constants are staged in LDS or read from global memory, and the
-  producer/consumer split;
+  producer/consumer split (for the quadratic kernel with three or six
+  producer waves);
 * batches: the persistent grid size.
 
 A probe run with a reduced sweep count times each candidate (the cost of a
@@ -50,7 +51,7 @@ def shape_key(info, replicas: int) -> str:
 def candidates(info):
     """(waves per workgroup, LDS residency, split) triples."""
     if info.variant == 0:
-        return [(1, -1, 0), (4, -1, 0), (4, -1, 1)]
+        return [(1, -1, 0), (4, -1, 0), (4, -1, 1), (4, -1, 2)]
     return [(w, r, 0) for w in (1, 2, 3, 4) for r in (0, 1)] + [(4, 1, 1)]
 
 

@@ -28,7 +28,7 @@
 
 namespace pbit {
 hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, hipStream_t stream);
-hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, hipStream_t stream);
+hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, int producers, hipStream_t stream);
 hipError_t launch_sweep_linear_pc_a(const DevInstance &d, bool wide, hipStream_t stream);
 hipError_t launch_sweep_linear_pc_b(const DevInstance &d, bool wide, hipStream_t stream);
 hipError_t launch_sweep_linear_pc_c(const DevInstance &d, bool wide, hipStream_t stream);
@@ -919,8 +919,12 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
     hipError_t e;
     switch (inst->plan.variant) {
         case kQuad: {
-            const bool pc = inst->split == 1 || (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus);
-            e = pc ? launch_sweep_quad_pc(d, inst->plan.nb, s) : launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
+            const bool pc = inst->split >= 1 || (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus);
+            // six producers (two waves per SIMD) pay off for instances of few
+            // blocks (measured: 4 blocks faster, 10 blocks slower than three)
+            const int producers = inst->split == 2 || (inst->split < 0 && inst->plan.nb <= 4) ? 6 : 3;
+            e = pc ? launch_sweep_quad_pc(d, inst->plan.nb, producers, s)
+                   : launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
             break;
         }
         default: {
@@ -1059,7 +1063,8 @@ pbit_status pbit_set_tiling(pbit_instance *inst, int32_t waves_per_block, int32_
     const bool ok = quad ? (wpb == 1 || wpb == 4) : (wpb >= 1 && wpb <= 4);
     if (!ok) return fail(PBIT_EINVAL, "waves per block must be 1 or 4 (quadratic) or 1..4 (linear)");
     if (lds_resident < -1 || lds_resident > 1) return fail(PBIT_EINVAL, "lds_resident must be -1, 0 or 1");
-    if (split < -1 || split > 1) return fail(PBIT_EINVAL, "split must be -1, 0 or 1");
+    if (split < -1 || split > (quad ? 2 : 1))
+        return fail(PBIT_EINVAL, "split must be -1, 0 or 1 (and 2 for the quadratic kernel)");
     if (split == 1 && !quad && linear_split_bytes(inst->plan) > kMaxLds)
         return fail(PBIT_ERANGE, "site constants do not fit LDS for the split layout");
     if (!quad && lds_resident == 1 && resident_bytes(inst->plan, wpb) > kMaxLds)

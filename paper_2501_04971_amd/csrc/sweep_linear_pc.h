@@ -49,7 +49,7 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int total = d.T * words;  // ring blocks per run
 
-    if (wave > 0) produce_thresholds(d, wave - 1, 0, 0, ring, th, kround, m2);
+    if (wave > 0) produce_thresholds<3>(d, wave - 1, 0, 0, ring, th, kround, m2);
     __syncthreads();
 
     // Every wave walks the same sequence of ring blocks and meets the others
@@ -116,7 +116,7 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
             }
         } else if (c + 1 < total) {
             const int t1 = (c + 1) / words, b1 = (c + 1) - t1 * words;
-            produce_thresholds(d, wave - 1, t1, b1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
+            produce_thresholds<3>(d, wave - 1, t1, b1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
         }
         buf ^= 1;
         __syncthreads();

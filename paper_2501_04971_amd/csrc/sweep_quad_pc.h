@@ -115,35 +115,38 @@ __device__ __forceinline__ int theta_floor_guess(uint32_t u)
     return min(max(p, 1), kThetaLen - 3);
 }
 
-// Producer p (0..2) fills the ring buffer of block blk (sites 32 blk ..
-// 32 blk + 31) of sweep t: Philox groups g = p, p + 3, p + 6 (four sites each).
-// Producer 2 has only two groups; it computes a third and discards it, so that
-// all three run the same code with no branch between the twelve table searches
-// and the scheduler can overlap them.  The table position of each draw comes
-// from theta_floor_guess, accepted only where the table confirms it; the rest
-// (flat tails, where many positions share a value: a few draws in 10^6) is
-// settled by an exact bisection over the whole table.  Sites at or beyond
-// N_ext never flip.
+// Producer p (0 .. NP-1 of NP = 3 or 6) fills its share of the ring buffer of
+// block blk (sites 32 blk .. 32 blk + 31) of sweep t: Philox groups g = p + NP k
+// (four sites each), k < KG = ceil(8 / NP).  A producer with fewer groups
+// computes the spare ones and discards them, so that all run the same code with
+// no branch between the table searches and the scheduler can overlap them.  The
+// table position of each draw comes from theta_floor_guess, accepted only where
+// the table confirms it; the rest (flat tails, where many positions share a
+// value: a few draws in 10^6) is settled by an exact bisection over the whole
+// table.  Sites at or beyond N_ext never flip.
+template <int NP>
 __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, int t, int blk, int64_t *ring,
                                                    const int32_t *th, uint32_t kround, uint64_t m2)
 {
+    constexpr int KG = (8 + NP - 1) / NP;
+    constexpr int E = 4 * KG;
     const int lane = threadIdx.x & 63;
     const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
-    uint32_t u[12];
-    int gs[12];
+    uint32_t u[E];
+    int gs[E];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < KG; ++k) {
         uint32_t rnd[4];
-        philox_block(cbase + (uint32_t)(blk * 8 + p + 3 * k), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
+        philox_block(cbase + (uint32_t)(blk * 8 + p + NP * k), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             u[4 * k + q] = rnd[q] >> 8;
             gs[4 * k + q] = theta_floor_guess(u[4 * k + q]);
         }
     }
-    int lo[12], hi[12];
+    int lo[E], hi[E];
 #pragma unroll
-    for (int e = 0; e < 12; ++e) {
+    for (int e = 0; e < E; ++e) {
         // fast path: check the guess and its neighbours against the table itself
         // (th is non-decreasing: within th[g - 1] <= u < th[g + 2] the position
         // is g - 1 plus the number of th[g], th[g + 1] that are <= u; bitwise
@@ -152,7 +155,7 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
         const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
                        t3 = (uint32_t)th[g + 2];
         const int found = g - 1 + (int)(t1 <= u[e]) + (int)(t2 <= u[e]);
-        const bool ok = ((t0 <= u[e]) & (u[e] < t3)) | (p + 3 * (e >> 2) >= 8);  // (a discarded group needs no search)
+        const bool ok = ((t0 <= u[e]) & (u[e] < t3)) | (p + NP * (e >> 2) >= 8);  // (a discarded group needs no search)
         lo[e] = ok ? found : 0;
         hi[e] = ok ? found : kThetaLen - 1;
     }
@@ -161,10 +164,10 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
     for (;;) {
         bool any = false;
 #pragma unroll
-        for (int e = 0; e < 12; ++e) any = any || lo[e] < hi[e];
+        for (int e = 0; e < E; ++e) any = any || lo[e] < hi[e];
         if (__ballot(any) == 0) break;
 #pragma unroll
-        for (int e = 0; e < 12; ++e) {
+        for (int e = 0; e < E; ++e) {
             if (lo[e] < hi[e]) {
                 const int mid = (lo[e] + hi[e] + 1) >> 1;
                 const bool le = (uint32_t)th[mid] <= u[e];
@@ -177,11 +180,11 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
     // ish <= 50 (the common case, uniform per instance)
     const bool nosat = d.ish <= 50;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (p + 3 * k < 8) {
+    for (int k = 0; k < KG; ++k) {
+        if (p + NP * k < 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int s = 4 * (p + 3 * k) + q;
+                const int s = 4 * (p + NP * k) + q;
                 const int js = lo[4 * k + q] + 1 - kThetaHalf;
                 const int64_t h = (nosat ? (int64_t)js * ((int64_t)1 << d.ish) : index_threshold(js, d.ish)) - d.irnd;
                 ring[s * 64 + lane] = blk * 32 + s < d.n_ext ? h : INT64_MAX;
@@ -193,38 +196,49 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
 // Producer p's share of the next J slab (quadratic kernel): loaded into
 // registers before the producer's other work of the block and stored after
 // it, so that the global loads' latency is hidden.
-template <int NB>
+template <int NB, int NP>
 constexpr int slab_pieces_per_producer()
 {
-    return (NB + 1 + 2) / 3;
+    return (NB + 1 + NP - 1) / NP;
 }
 
-template <int NB>
-__device__ __forceinline__ void load_slab(int p, const int8_t *jsrc, uint4 (&pf)[slab_pieces_per_producer<NB>()])
+template <int NB, int NP>
+__device__ __forceinline__ void load_slab(int p, const int8_t *jsrc, uint4 (&pf)[slab_pieces_per_producer<NB, NP>()])
 {
     constexpr int PIECES = NB + 1;
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int j = 0; j < slab_pieces_per_producer<NB>(); ++j)
-        pf[j] = *reinterpret_cast<const uint4 *>(jsrc + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16);
+    for (int j = 0; j < slab_pieces_per_producer<NB, NP>(); ++j)
+        pf[j] = *reinterpret_cast<const uint4 *>(jsrc + min(p + NP * j, PIECES - 1) * 1024 + lane * 16);
 }
 
-template <int NB>
-__device__ __forceinline__ void store_slab(int p, int8_t *ldst, const uint4 (&pf)[slab_pieces_per_producer<NB>()])
+template <int NB, int NP>
+__device__ __forceinline__ void store_slab(int p, int8_t *ldst, const uint4 (&pf)[slab_pieces_per_producer<NB, NP>()])
 {
     constexpr int PIECES = NB + 1;
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int j = 0; j < slab_pieces_per_producer<NB>(); ++j)
-        *reinterpret_cast<uint4 *>(ldst + min(p + 3 * j, PIECES - 1) * 1024 + lane * 16) = pf[j];
+    for (int j = 0; j < slab_pieces_per_producer<NB, NP>(); ++j)
+        *reinterpret_cast<uint4 *>(ldst + min(p + NP * j, PIECES - 1) * 1024 + lane * 16) = pf[j];
 }
 
-// One annealing run of replicas rbase + [0, 64) by a workgroup of 4 waves
-// (wave 0 consumer, waves 1-3 producers), then the scoring of the final states.
-// smem must hold quad_pc_lds_bytes<NB>() bytes.
-template <int NB>
+// Waves of the split workgroup for PR producers: wave 0 visits; with PR = 3
+// waves 1-3 produce; with PR = 6 waves 1-3 and 5-7 produce and wave 4 (which
+// shares the visiting wave's SIMD, waves being placed round-robin) only takes
+// part in the barriers.
+template <int PR>
+constexpr int quad_pc_waves()
+{
+    return PR == 3 ? 4 : 8;
+}
+
+// One annealing run of replicas rbase + [0, 64) by a workgroup of
+// quad_pc_waves<PR>() waves, then the scoring of the final states.  smem must
+// hold quad_pc_lds_bytes<NB>() bytes.
+template <int NB, int PR>
 __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, unsigned char *smem)
 {
+    static_assert(PR == 3 || PR == 6, "3 or 6 producers");
     constexpr int NP = NB * 32;
     constexpr int LS = NP + 16;
     constexpr int SLAB = 1024 * (NB + 1);
@@ -254,7 +268,9 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int total = d.T * NB;
 
-    if (wave > 0) produce_thresholds(d, wave - 1, 0, 0, ring, th, kround, m2);
+    const bool producer = wave > 0 && !(PR == 6 && wave == 4);
+    const int pi = PR == 6 && wave > 4 ? wave - 2 : wave - 1;  // producer index 0 .. PR-1
+    if (producer) produce_thresholds<PR>(d, pi, 0, 0, ring, th, kround, m2);
     __syncthreads();
 
     uint32_t x[NB][8];
@@ -315,15 +331,15 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             }
             rotate_chunks<NB>(x);
             fields_from_acc(nf.acc0, nf.acc1, v.F);
-        } else {
+        } else if (producer) {
             // the next block's thresholds, and the slab of the block after it
             // (at the end: slabs 0 and 1 for the scoring pass, no thresholds)
             const int t1 = (c + 1) / NB, blk1 = (c + 1) - t1 * NB;
             const int blk2 = (c + 2) % NB;
-            uint4 pf[slab_pieces_per_producer<NB>()];
-            load_slab<NB>(wave - 1, d.J + (size_t)blk2 * SLAB, pf);
-            if (c + 1 < total) produce_thresholds(d, wave - 1, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
-            store_slab<NB>(wave - 1, slabs + b2 * SLAB, pf);
+            uint4 pf[slab_pieces_per_producer<NB, PR>()];
+            load_slab<NB, PR>(pi, d.J + (size_t)blk2 * SLAB, pf);
+            if (c + 1 < total) produce_thresholds<PR>(d, pi, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
+            store_slab<NB, PR>(pi, slabs + b2 * SLAB, pf);
         }
         buf ^= 1;
         b0 = b1;

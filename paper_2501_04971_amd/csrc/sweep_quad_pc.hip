@@ -5,22 +5,25 @@ namespace pbit {
 
 static_assert(quad_pc_lds_bytes<kMaxQuadBlocks>() <= 160 * 1024, "split layout exceeds the LDS of a CU");
 
-template <int NB>
-__global__ __launch_bounds__(256) void sweep_quad_pc(const DevInstance d)
+template <int NB, int PR>
+__global__ __launch_bounds__(quad_pc_waves<PR>() * kWave) void sweep_quad_pc(const DevInstance d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    quad_run_pc<NB>(d, blockIdx.x * kWave, smem);
+    quad_run_pc<NB, PR>(d, blockIdx.x * kWave, smem);
 }
 
 #define PBIT_QUAD_PC_CASE(nb)                                                               \
     case nb:                                                                                \
-        kern = reinterpret_cast<const void *>(&sweep_quad_pc<nb>);                          \
+        kern = producers == 6 ? reinterpret_cast<const void *>(&sweep_quad_pc<nb, 6>)      \
+                              : reinterpret_cast<const void *>(&sweep_quad_pc<nb, 3>);     \
         lds = quad_pc_lds_bytes<nb>();                                                      \
         break;
 
-// One workgroup of 4 waves per 64 replicas.
-hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, hipStream_t stream)
+// One workgroup per 64 replicas, with 3 producer waves (4 waves in all) or 6
+// (8 waves).
+hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, int producers, hipStream_t stream)
 {
+    if (producers != 3 && producers != 6) return hipErrorInvalidValue;
     const void *kern = nullptr;
     size_t lds = 0;
     switch (nb) {
@@ -33,8 +36,9 @@ hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, hipStream_t stream
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int blocks = (d.R + kWave - 1) / kWave;
+    const int threads = (producers == 6 ? quad_pc_waves<6>() : quad_pc_waves<3>()) * kWave;
     void *args[] = {const_cast<DevInstance *>(&d)};
-    return hipLaunchKernel(kern, dim3(blocks), dim3(4 * kWave), args, lds, stream);
+    return hipLaunchKernel(kern, dim3(blocks), dim3(threads), args, lds, stream);
 }
 
 }  // namespace pbit

@@ -19,7 +19,7 @@ def test_keys_candidates_and_cache(tmp_path):
     assert iq.n_pad == (iq.n_ext + 31) // 32 * 32
     assert A.shape_key(iq, 300) == f"v0-n{iq.n_pad}-m1-r512"
     assert A.shape_key(im, 300).startswith("v1-n") and A.shape_key(im, 300).endswith("-m7-r512")
-    assert A.candidates(iq) == [(1, -1, 0), (4, -1, 0), (4, -1, 1)]
+    assert A.candidates(iq) == [(1, -1, 0), (4, -1, 0), (4, -1, 1), (4, -1, 2)]
     assert len(A.candidates(im)) == 9
     path = str(tmp_path / "t.json")
     assert A.load_cache(path) == {}

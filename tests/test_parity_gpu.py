@@ -187,7 +187,7 @@ def test_every_tiling_is_bit_identical(need_gpu, case):
     if case == "qkp97":
         prob = G.qkp(97, Fraction(3, 4), G.rng_for(950, 0))
         par = G.Params(replicas=300, sweeps=30, beta=Fraction(5), eta=Fraction(20))
-        layouts = [(1, -1, 0), (4, -1, 0), (4, -1, 1)]
+        layouts = [(1, -1, 0), (4, -1, 0), (4, -1, 1), (4, -1, 2)]
     else:
         if case == "mkp120x12wide":
             rng = G.rng_for(950, 3)
