@@ -14,13 +14,22 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // numbers: as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 products
 // with the Weyl key schedule.  The counter's third word is the replica, fixed
 // for a lane, so its first-round product m2 = 0xCD9E8D57 * c2 is passed in.
+// a ^ b ^ k in one instruction (gfx950 three-input bitwise op, truth table
+// 0x96); k is a key word, uniform across the wave, so it is read as a scalar.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint64_t m2, uint32_t c3,
                                              uint32_t k0, uint32_t k1, uint32_t out[4])
 {
     const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
-    uint32_t x0 = (uint32_t)(m2 >> 32) ^ c1 ^ k0;
+    uint32_t x0 = xor3_key((uint32_t)(m2 >> 32), c1, k0);
     uint32_t x1 = (uint32_t)m2;
-    uint32_t x2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+    uint32_t x2 = xor3_key((uint32_t)(m0 >> 32), c3, k1);
     uint32_t x3 = (uint32_t)m0;
 #pragma unroll
     for (int rd = 1; rd < 10; ++rd) {
@@ -28,8 +37,8 @@ __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint64_t 
         k1 += 0xBB67AE85u;
         const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        const uint32_t y0 = xor3_key((uint32_t)(p1 >> 32), x1, k0);
+        const uint32_t y2 = xor3_key((uint32_t)(p0 >> 32), x3, k1);
         x1 = (uint32_t)p1;
         x3 = (uint32_t)p0;
         x0 = y0;
