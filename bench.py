@@ -44,7 +44,7 @@ LDS_PEAK = 256 * 128 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2)
 # and WRITE_SIZE (x1) passes (calibrated on a 256 MiB copy); valid for the
 # kernel build they were taken on, keyed by kernel and workload.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("sweep_quad_pc<10, 3>", 2): (864.375 * 2 + 224) * 1024}
 
 WORKLOAD_NAMES = {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10", 2: "QKP N=300 d=1.0",
                   3: "mixed batch: 256 QKP + 256 MKP, 256 replicas each"}
