@@ -242,7 +242,25 @@ def test_maximum_shapes(need_gpu):
     q = G.qkp(336, Fraction(1, 2), G.rng_for(961, 0))
     info = B.pbit_plan(q, G.Params())
     assert info.n_pad == 352, info.n_pad
-    run_parity(q, G.Params(replicas=64, sweeps=8, beta=Fraction(5), eta=Fraction(20)), 2, label="QKP NB=11")
+    qpar = G.Params(replicas=64, sweeps=8, beta=Fraction(5), eta=Fraction(20))
+    run_parity(q, qpar, 2, label="QKP NB=11")
+    # the split layout with six producers at the largest block count, and with
+    # three at the smallest (one block)
+    for prob, par, split in ((q, qpar, 2),
+                             (G.qkp(20, Fraction(1), G.rng_for(961, 3)),
+                              G.Params(replicas=70, sweeps=12, beta=Fraction(5), eta=Fraction(20)), 1)):
+        say(f"[parity] QKP n={prob.n} split={split}")
+        ref = O.saim(prob, par, 2, nthreads=NTHREADS)
+        inst = B.Instance(prob, par)
+        inst.set_tiling(4, -1, split)
+        for k in range(2):
+            lam = inst.get_lambda()
+            inst.sample_round()
+            out = inst.round_outputs()
+            inst.update_lambda()
+            out["lq"] = lam
+            assert_round_equal(ref["program"], ref["rounds"][k], out, k)
+        inst.close()
     m32 = G.mkp(120, 32, G.rng_for(961, 1))
     run_parity(m32, G.Params(replicas=64, sweeps=6, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5)), 2,
                label="MKP M=32")
