@@ -1,8 +1,8 @@
 // Producer/consumer form of the quadratic annealing run, for launches that
 // leave SIMDs idle (one wave of 64 replicas per CU): a workgroup is one
-// consumer wave that walks the sites of its 64 replicas, plus three producer
-// waves on the CU's other SIMDs that do the part of every visit that does not
-// depend on the state, one block of 32 sites ahead:
+// consumer wave that walks the sites of its 64 replicas, plus three (or six,
+// two per SIMD) producer waves on the CU's other SIMDs that do the part of
+// every visit that does not depend on the state, one block of 32 sites ahead:
 //
 //  * the Philox4x32-10 draw u24 of the visit (same counters as everywhere);
 //  * its threshold index j* = min{ j : Theta[j] > u24 } (Theta is
@@ -13,12 +13,14 @@
 //      hi = floor((Z B_t + 2^(S'-1)) / 2^32),  idx = clamp(floor(hi / 2^ish)),
 //    and -2304 < j* <= 2304, [idx >= j*] = [hi >= j* 2^ish];  |hi| < 2^62, so
 //    j* 2^ish is saturated to +-2^62 where it would not fit;
-//  * the refill of the next block's J slab.
+//  * the refill of the J slab two blocks ahead.
 //
 // The consumer's visit is then field, one 32x32->64 product and a 64-bit
 // compare; the per-site thresholds arrive through a double-buffered LDS ring
 // (32 sites x 64 lanes x 8 bytes per block) and one workgroup barrier per
-// block hands buffers over.  Results are bit-identical to sweep_quad.
+// block hands buffers over.  The consumer also issues the next block's field
+// refresh on the matrix cores while it visits the current block (see
+// NextFields).  Results are bit-identical to sweep_quad.
 #pragma once
 #include "sweep_quad.h"
 
