@@ -46,6 +46,12 @@ LDS_PEAK = 256 * 128 * 2.4e9
 # kernel build they were taken on, keyed by kernel and workload.
 MEASURED_TRAFFIC = {("sweep_quad_pc<10, 3>", 2): (864.375 * 2 + 224) * 1024}
 
+# LDS-pipe and matrix-core activity of the same kernel builds from rocprofv3 SQ
+# counters (SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, SQ_VALU_MFMA_BUSY_CYCLES),
+# as fractions of the cycles of the CUs the launch occupies.
+MEASURED_UTIL = {("sweep_quad_pc<10, 3>", 2): {"lds_pipe_active": 0.260, "lds_bank_conflict_share": 0.41,
+                                               "mfma_busy": 0.099}}
+
 WORKLOAD_NAMES = {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10", 2: "QKP N=300 d=1.0",
                   3: "mixed batch: 256 QKP + 256 MKP, 256 replicas each"}
 
@@ -256,6 +262,7 @@ def main() -> int:
             "waves": waves,
             "frac_of_occupied_simds": achieved / (ALU_PEAK_OPS * min(1.0, waves / SIMDS)),
             "secondary": secondary,
+            "rocprof_utilization": None if batch else MEASURED_UTIL.get((kernel, args.workload)),
         },
         "wall_s": wall,
         "best_feasible_profit": None if best is None else best[0],
