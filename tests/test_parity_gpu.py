@@ -269,3 +269,25 @@ def test_maximum_shapes(need_gpu):
     assert 1900 < B.pbit_plan(big, par).n_ext <= 2048
     say("[parity] MKP n=1400 M=32, sampled replicas")
     _spot_check_round0(big, par, [0, 77, 127])
+
+
+def test_tiling_choices_are_validated(need_gpu):
+    """Layouts a kernel does not have are refused on the host, before any launch,
+    and leave the instance usable."""
+    q = G.family0(1)
+    par = G.Params(replicas=64, sweeps=4, beta=Fraction(5), eta=Fraction(20))
+    inst = B.Instance(q, par)
+    for bad in [(2, -1, 0), (4, -1, 3), (4, 2, 0), (4, -1, -2)]:
+        with pytest.raises(B.PbitError):
+            inst.set_tiling(*bad)
+    inst.set_tiling(4, -1, 2)
+    inst.sample_round()
+    inst.close()
+    m = G.mkp(60, 5, G.rng_for(962, 0))
+    inst = B.Instance(m, G.Params(replicas=64, sweeps=4, beta=Fraction(50), alpha=Fraction(5)))
+    for bad in [(5, 0, 0), (4, -1, 2)]:
+        with pytest.raises(B.PbitError):
+            inst.set_tiling(*bad)
+    inst.set_tiling(4, 1, 1)
+    inst.sample_round()
+    inst.close()
