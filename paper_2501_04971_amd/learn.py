@@ -174,7 +174,7 @@ class Trainer:
         self.forward(d)
         lam = torch.zeros(count * 32, dtype=torch.int32, device="cuda")
         B.pbit_net_to_lambda(d["t"], d["scale"], d["dest"], d["sets"], lam)
-        return lam
+        return lam.view(count, 32)
 
 
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "lambda0_qkp.npz")
