@@ -156,7 +156,8 @@ def test_batch_workload3_sampled(need_gpu):
     batch.run(1, use_graph=True)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
-    picks = [0, 1, 2, 3] + [int(v) for v in rng.choice(np.arange(4, 512), 6, replace=False)]
+    # 7, 21 and 51 are MKP members that take the 64-bit dot kernels (N=250 M=30, N=500 M=30, N=500 M=10)
+    picks = [0, 1, 2, 3, 7, 21, 51] + [int(v) for v in rng.choice(np.arange(4, 512), 6, replace=False)]
     for i in picks:
         prob, par, K = members[i]
         prog = O.build_program(prob, par)
