@@ -63,11 +63,23 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
         g[k] = -(int32_t)d.b[k];
         sk[k] = 0u;
     }
+    // The slack layout is read once and the next block's beta multiplier one block
+    // ahead: inside the persistent batch loop the compiler must assume that the
+    // previous item's stores may alias these constants, so a load in the sweep would
+    // be a vector load waited on at the top of the visit chain.
+    int soff[M], sq[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        soff[k] = d.slack_off[k];
+        sq[k] = d.slack_q[k];
+    }
+    int32_t Bnext = d.Btab[0];
     int buf = 0;
     for (int c = 0; c < total; ++c) {
-        const int t = c / words, w = c - (c / words) * words;
+        const int w = c - (c / words) * words;
         if (wave == 0) {
-            const int32_t Bt = d.Btab[t];
+            const int32_t Bt = Bnext;
+            Bnext = d.Btab[(c + 1 < total ? c + 1 : c) / words];
             const int64_t *rg = ring + buf * 32 * 64;
             const int base = w * 32;
             if (w < owords) {
@@ -99,8 +111,8 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
             if (lo < hi) {
 #pragma unroll
                 for (int k = 0; k < M; ++k) {
-                    const int off = d.slack_off[k];
-                    const int q0 = max(0, lo - off), q1 = min(d.slack_q[k], hi - off);
+                    const int off = soff[k];
+                    const int q0 = max(0, lo - off), q1 = min(sq[k], hi - off);
                     const uint32_t sk0 = sk[k];
                     for (int q = q0; q < q1; ++q) {
                         const int i = off + q;
