@@ -1139,14 +1139,15 @@ pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *para
     if (cus < 1) cus = 1;
     // Which linear members run as split tiles: a split tile visits about twice
     // as fast but takes four waves per 64 replicas, i.e. twice the work per
-    // replica.  Members whose plain chain exceeds the average linear load per
-    // CU by a quarter would bound the round, so they are split (a threshold
-    // chosen by measurement on the mixed workload: splitting fewer or more
-    // members both lengthened its rounds).
+    // replica.  Only members whose plain chain exceeds twice the average linear
+    // load per CU would bound the round, so only they are split (a threshold
+    // chosen by measurement on the mixed workload, where it splits the N=500
+    // M=30 members: splitting also those at about 1.9 times the load, or none,
+    // both lengthened its rounds).
     std::vector<char> split(count, 0);
     const int64_t load = lin_total / cus;
     for (int i = 0; i < count; ++i)
-        split[i] = lin_cost[i] > load + load / 4 && linear_split_bytes(b->members[i]->plan) <= kMaxLds;
+        split[i] = lin_cost[i] > 2 * load && linear_split_bytes(b->members[i]->plan) <= kMaxLds;
     for (int i = 0; i < count; ++i) {
         const Plan &P = b->members[i]->plan;
         const int code = batch_variant_code(P.variant, P.nb, P.m);
