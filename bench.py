@@ -44,7 +44,7 @@ LDS_PEAK = 256 * 128 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2)
 # and WRITE_SIZE (x1) passes (calibrated on a 256 MiB copy); valid for the
 # kernel build they were taken on, keyed by kernel and workload.
-MEASURED_TRAFFIC = {("sweep_quad_pc<10, 3>", 2): (864.375 * 2 + 224) * 1024}
+MEASURED_TRAFFIC = {("sweep_quad_pc<10, 3>", 2): (863.9375 * 2 + 224) * 1024}
 
 # LDS-pipe and matrix-core activity of the same kernel builds from rocprofv3 SQ
 # counters (SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, SQ_VALU_MFMA_BUSY_CYCLES),
