@@ -73,7 +73,9 @@ typedef struct {
 
 /* Sampler settings (Sec. III-B and Table 1).
  *  replicas     R independent chains per round; they share lambda.
- *  sweeps       T Monte-Carlo sweeps per annealing run (>= 1).
+ *  sweeps       T Monte-Carlo sweeps per annealing run (>= 1, and
+ *               T * ceil(N_ext / 4) <= 2^32 so that the Philox counter word
+ *               t * ceil(N_ext / 4) + i / 4 never wraps; PBIT_ERANGE otherwise).
  *  beta         beta_max of the linear schedule beta_t = beta_max t/(T-1).
  *  eta          multiplier step size (Algorithm 1); lambda += eta * mean_r g_r / s_g.
  *  p_q          256*P directly, or -1 for the rule P = alpha d N.
@@ -104,7 +106,7 @@ typedef struct {
     int32_t reserved;
     size_t workspace_bytes;
     /* layout of the buffer filled by pbit_round_outputs (byte offsets) */
-    size_t out_x, out_g, out_profit, out_feasible, out_G, out_lambda, out_round, out_bytes;
+    size_t out_x, out_g, out_profit, out_feasible, out_G, out_lambda, out_round, out_sat, out_bytes;
 } pbit_plan_info;
 
 /* Compiles the instance on the host and describes it.  Defines the encoding of
@@ -169,7 +171,10 @@ pbit_status pbit_best_feasible(pbit_instance *inst, int64_t *profit, uint8_t *x,
  *   out_feasible int32  [R]         1 if weight*x <= capacity
  *   out_G        int64  [m]         sum of residuals over replicas
  *   out_lambda   int32  [m]         lambda_q in force for the next round
- *   out_round    int32  [1]         rounds completed */
+ *   out_round    int32  [1]         rounds completed
+ *   out_sat      uint32 [1]         bit k set once lambda_k has been held at
+ *                                   +-lq_max by a step or a set (sticky): from
+ *                                   then on it no longer follows Algorithm 1 */
 pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes, pbit_stream stream);
 
 /* Releases host-side state; the workspace may be reused afterwards.  Does not
@@ -259,8 +264,9 @@ pbit_status pbit_batch_set_lambdas(pbit_batch *batch, const int32_t *lambda_q, p
 
 /* Writes one 160-byte record per member to dev_out (device memory), ordered
  * on stream: int64 best feasible profit; int32 its round, 1 if any feasible
- * sample exists, rounds done, feasible samples in the last round, two zero
- * words; int32 lambda_q[32] (zero beyond m). */
+ * sample exists, rounds done, feasible samples in the last round, the
+ * multiplier saturation mask (out_sat of pbit_round_outputs), one zero
+ * word; int32 lambda_q[32] (zero beyond m). */
 pbit_status pbit_batch_snapshot(pbit_batch *batch, void *dev_out, pbit_stream stream);
 
 /* Releases the batch, its members and its graph.  Does not synchronise. */

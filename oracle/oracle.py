@@ -171,6 +171,11 @@ def build_program(prob: Problem, par: Params) -> Program:
     T = int(par.sweeps)
     if T < 1:
         raise ValueError("sweeps must be >= 1")
+    # the Philox counter's first word is t * ceil(N_ext / 4) + i / 4; it must not
+    # wrap, or later sweeps would reuse earlier sweeps' draws (Sec. III-B asks
+    # for an independent random number at every update)
+    if T * ((n_ext + 3) // 4) > (1 << 32):
+        raise OracleRangeError("sweeps x site groups exceed the 32-bit counter word")
     beta = Fraction(par.beta)
     if beta < 0:
         raise ValueError("beta must be >= 0")
@@ -272,6 +277,15 @@ def lambda_step(prog: Program, lam_acc: list, G: list, R: int | None = None):
         new_acc.append(acc)
         lq.append(round_half_away(Fraction(acc, 1 << 24)))
     return new_acc, lq
+
+
+def saturation_mask(acc: list, cap: int, mask: int) -> int:
+    """Sticky bit mask of the multipliers that sit at the accumulator bound: from
+    there on the step of Algorithm 1 is no longer followed exactly."""
+    for k, a in enumerate(acc):
+        if abs(int(a)) == cap:
+            mask |= 1 << k
+    return mask
 
 
 # ---------------------------------------------------------------------------
@@ -376,6 +390,19 @@ def sa_round(prog: Program, lq, k: int, r0: int = 0, nrep: int | None = None,
 
 
 # ---------------------------------------------------------------------------
+# best feasible sample (Algorithm 1: keep the feasible samples, return the best)
+
+def best_update(best, k: int, profit, feasible, x):
+    """Best record after round k: the largest profit over feasible samples; among
+    equal profits the earliest round wins, then the lowest replica.  best is
+    None or (profit, round, replica, original bits)."""
+    for r in range(len(profit)):
+        if feasible[r] and (best is None or int(profit[r]) > best[0]):
+            best = (int(profit[r]), k, r, np.asarray(x[r]).copy())
+    return best
+
+
+# ---------------------------------------------------------------------------
 # the whole loop
 
 def saim(prob: Problem, par: Params, rounds: int, lq0=None, nthreads: int | None = None,
@@ -387,18 +414,19 @@ def saim(prob: Problem, par: Params, rounds: int, lq0=None, nthreads: int | None
     lq = [0] * prog.m if lq0 is None else [int(v) for v in lq0]
     lq = [max(-prog.lq_max, min(prog.lq_max, v)) for v in lq]
     acc = [v << 24 for v in lq]
+    cap = prog.lq_max << 24
+    sat = saturation_mask(acc, cap, 0) if lq0 is not None else 0
     best = None
     log = []
     for k in range(rounds):
         x, g = sa_round(prog, lq, k, 0, prog.R, nthreads)
         profit, feas = score(prog, x)
-        for r in range(prog.R):
-            if feas[r] and (best is None or int(profit[r]) > best[0]):
-                best = (int(profit[r]), k, r, x[r, :prog.n].copy())
+        best = best_update(best, k, profit, feas, x[:, :prog.n])
         G = [int(v) for v in g.sum(axis=0)]
-        entry = {"lq": list(lq), "G": G, "feasible": int(feas.sum())}
+        entry = {"lq": list(lq), "G": G, "feasible": int(feas.sum()), "sat": sat}
         if keep_states:
             entry.update(x=x, g=g, profit=profit, feasible_mask=feas)
         log.append(entry)
         acc, lq = lambda_step(prog, acc, G)
-    return {"program": prog, "rounds": log, "best": best, "lq": lq, "acc": acc}
+        sat = saturation_mask(acc, cap, sat)
+    return {"program": prog, "rounds": log, "best": best, "lq": lq, "acc": acc, "sat": sat}

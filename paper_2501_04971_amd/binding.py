@@ -54,7 +54,8 @@ class pbit_plan_info(ctypes.Structure):
                 ("out_x", ctypes.c_size_t), ("out_g", ctypes.c_size_t),
                 ("out_profit", ctypes.c_size_t), ("out_feasible", ctypes.c_size_t),
                 ("out_G", ctypes.c_size_t), ("out_lambda", ctypes.c_size_t),
-                ("out_round", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t)]
+                ("out_round", ctypes.c_size_t), ("out_sat", ctypes.c_size_t),
+                ("out_bytes", ctypes.c_size_t)]
 
 
 EXPORTS = {
@@ -360,6 +361,7 @@ class Instance:
             "G": view(i.out_G, np.int64, m).copy(),
             "lambda_q": view(i.out_lambda, np.int32, m).copy(),
             "round": int(view(i.out_round, np.int32, 1)[0]),
+            "lambda_saturated": int(view(i.out_sat, np.uint32, 1)[0]),
         }
 
     def close(self):
@@ -391,6 +393,7 @@ def decode_snapshot(raw: np.ndarray, count: int) -> dict:
     return {"best": r[:, :8].copy().view(np.int64).reshape(count),
             "best_round": head[:, 0], "has_feasible": head[:, 1].astype(bool),
             "rounds": head[:, 2], "feasible_last": head[:, 3],
+            "lambda_saturated": head[:, 4].view(np.uint32),
             "lambda_q": r[:, 32:].copy().view(np.int32).reshape(count, MAX_M)}
 
 

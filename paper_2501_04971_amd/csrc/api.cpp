@@ -243,6 +243,10 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     P.owords = (n + 31) / 32;
     P.nq = (n_ext + 3) / 4;
     if (P.words > kMaxWords) return fail(PBIT_ERANGE, "more than 2048 spins");
+    // Philox counter word 0 is t * nq + i / 4 (uint32): a wrap would replay
+    // earlier sweeps' draws instead of a fresh one per update (Sec. III-B)
+    if ((uint64_t)P.T * (uint64_t)P.nq > ((uint64_t)1 << 32))
+        return fail(PBIT_ERANGE, "sweeps x ceil(n_ext / 4) exceed the 32-bit Philox counter word");
     P.n_rec = P.words * 32 + 32;
     P.acol.assign((size_t)P.n_rec * m, 0);
     for (int k = 0; k < m; ++k) {
@@ -495,6 +499,7 @@ void fill_plan_info(const Plan &P, pbit_plan_info *out)
     out->out_G = put((size_t)P.m * 8);
     out->out_lambda = put((size_t)P.m * 4);
     out->out_round = put(4);
+    out->out_sat = put(4);
     out->out_bytes = o;
 }
 
@@ -652,6 +657,7 @@ pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *
     d.best = reinterpret_cast<int64_t *>(base + L.best);
     d.best_x = reinterpret_cast<uint32_t *>(base + L.best_x);
     d.feas_count = reinterpret_cast<int32_t *>(base + L.feas);
+    d.lam_sat = reinterpret_cast<uint32_t *>(base + L.feas + 4);  // same 256-byte slot
     d.rx = reinterpret_cast<uint32_t *>(base + L.rx);
     d.rg = reinterpret_cast<int32_t *>(base + L.rg);
     d.rprofit = reinterpret_cast<int64_t *>(base + L.rprofit);
@@ -1030,7 +1036,7 @@ pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes,
         {info.out_x, d.rx, (size_t)P.R * P.words * 4}, {info.out_g, d.rg, (size_t)P.R * P.m * 4},
         {info.out_profit, d.rprofit, (size_t)P.R * 8}, {info.out_feasible, d.rfeas, (size_t)P.R * 4},
         {info.out_G, d.G, (size_t)P.m * 8},            {info.out_lambda, d.lam_q, (size_t)P.m * 4},
-        {info.out_round, d.round_k, 4},
+        {info.out_round, d.round_k, 4},                {info.out_sat, d.lam_sat, 4},
     };
     for (const Piece &pc : pieces) {
         hipError_t e = hipMemcpyAsync(o + pc.off, pc.src, pc.bytes, hipMemcpyDeviceToDevice, s);

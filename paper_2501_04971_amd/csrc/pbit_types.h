@@ -39,6 +39,7 @@ struct DevInstance {
     int64_t *best;            // [4] profit, round, replica, valid
     uint32_t *best_x;         // [words]
     int32_t *feas_count;      // [1] feasible replicas of the last round
+    uint32_t *lam_sat;        // [1] bit k set once lambda_k has been held at +-lq_max (sticky)
     int32_t *rounds_left;     // [1] multiplier steps still to run (batch members), or null
     // per-replica outputs of the last round
     uint32_t *rx;             // [R][words]

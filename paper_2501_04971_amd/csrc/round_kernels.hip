@@ -123,6 +123,9 @@ __device__ __forceinline__ void lambda_update_body(const DevInstance &d, int mod
         if (mode == 2) acc = (int64_t)vals[tid] * (1 << 24);
         acc = acc > cap ? cap : acc;
         acc = acc < -cap ? -cap : acc;
+        // a multiplier held at the bound no longer follows Algorithm 1's step:
+        // flag it (sticky) so the caller can tell
+        if (mode != 0 && (acc == cap || acc == -cap)) atomicOr(d.lam_sat, 1u << tid);
         const int32_t q = acc >= 0 ? (int32_t)((acc + (1 << 23)) >> 24)
                                    : -(int32_t)((-acc + (1 << 23)) >> 24);
         d.lam_acc[tid] = acc;
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(64) void batch_snapshot(const DevInstance *insts, u
         h[1] = (int32_t)d.best[3];
         h[2] = d.round_k[0];
         h[3] = d.feas_count[0];
-        h[4] = 0;
+        h[4] = (int32_t)d.lam_sat[0];
         h[5] = 0;
     }
     if (tid < kMaxM) reinterpret_cast<int32_t *>(rec + 32)[tid] = tid < d.m ? d.lam_q[tid] : 0;

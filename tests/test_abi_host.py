@@ -130,3 +130,25 @@ def test_batch_sizes_and_member_errors(lib):
     h = ctypes.c_void_p()
     st = lib.pbit_create_batch(ms.problems, ms.params, 2, None, 0, None, 0, None, ctypes.byref(h))
     assert st == B.PBIT_EINVAL and b"member 1" in lib.pbit_last_error()
+
+
+def test_philox_counter_bound_at_the_boundary(lib):
+    """Sweeps x ceil(n_ext/4) beyond 2^32 would wrap the counter word
+    t ceil(n_ext/4) + i/4 and replay draws: PBIT_ERANGE, exactly where the
+    oracle refuses the same settings."""
+    prob = G.mkp(1400, 32, G.rng_for(961, 2))
+    par = G.Params(replicas=1, sweeps=1, beta=Fraction(50), alpha=Fraction(5))
+    nq = (B.pbit_plan(prob, par).n_ext + 3) // 4
+    T_ok = (1 << 32) // nq
+    assert T_ok < (1 << 24)
+    B.pbit_plan(prob, G.Params(replicas=1, sweeps=T_ok, beta=Fraction(50), alpha=Fraction(5)))
+    _expect(B.PBIT_ERANGE, prob, G.Params(replicas=1, sweeps=T_ok + 1, beta=Fraction(50), alpha=Fraction(5)))
+    with pytest.raises(O.OracleRangeError):
+        O.build_program(prob, G.Params(replicas=1, sweeps=T_ok + 1, beta=Fraction(50), alpha=Fraction(5)))
+
+
+def test_round_output_layout_has_the_saturation_word(lib):
+    prob, par, _ = G.workload(0, 0)
+    info = B.pbit_plan(prob, par)
+    assert info.out_round < info.out_sat < info.out_bytes
+    assert info.out_sat % 256 == 0

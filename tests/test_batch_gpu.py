@@ -145,31 +145,44 @@ def test_batch_member_set_lambda(need_gpu):
 
 def test_batch_workload3_sampled(need_gpu):
     """The full mixed workload (512 members: 256 QKP N in U{100..300}, 256 MKP N in
-    {100,250,500} x M in {5,10,30}, 256 replicas each) for one graph round; sampled
-    replicas of sampled members are replayed by the oracle."""
+    {100,250,500} x M in {5,10,30}, 256 replicas each) for two graph rounds.  For
+    sampled members, sampled replicas of round 0 (lambda = 0) and of round 1
+    (under the multipliers the first step gave, checked against the oracle's
+    step) are replayed by the oracle."""
     import torch
     members = [G.workload(3, i) for i in range(512)]
     batch = B.Batch([p for p, _, _ in members], [q for _, q, _ in members],
                     rounds=[K for _, _, K in members])
     items, nblk, lds = batch.shape()
     say(f"[batch] workload 3: items={items} blocks={nblk} lds={lds}")
-    batch.run(1, use_graph=True)
-    torch.cuda.synchronize()
     rng = np.random.default_rng(5)
     # 7, 21 and 51 are MKP members that take the 64-bit dot kernels (N=250 M=30, N=500 M=30, N=500 M=10)
     picks = [0, 1, 2, 3, 7, 21, 51] + [int(v) for v in rng.choice(np.arange(4, 512), 6, replace=False)]
-    for i in picks:
-        prob, par, K = members[i]
-        prog = O.build_program(prob, par)
-        got = batch.members[i].round_outputs()
-        reps = sorted({0, 255, int(rng.integers(1, 255))})
-        say(f"[batch] member {i} {prob.name} replicas {reps}")
-        for r in reps:
-            x, g = O.sa_round(prog, [0] * prob.m, 0, r, 1, 1)
-            xb = B.unpack_bits(got["x_bits"][r:r + 1], prog.n_ext)
-            assert (xb[0] == x[0]).all(), f"member {i} replica {r}: state differs"
-            assert (got["g"][r, :prob.m] == g[0]).all()
-        # the residual sums are the sums of the per-replica residuals
-        assert (got["G"] == got["g"].astype(np.int64).sum(axis=0)).all()
-        assert got["round"] == 1
+    reps = {i: sorted({0, 255, int(rng.integers(1, 255))}) for i in picks}
+    progs = {i: O.build_program(members[i][0], members[i][1]) for i in picks}
+    acc = {i: [0] * members[i][0].m for i in picks}
+    lq = {i: [0] * members[i][0].m for i in picks}
+    moved = set()
+    for k in range(2):
+        batch.run(1, use_graph=True)
+        torch.cuda.synchronize()
+        for i in picks:
+            prob, par, K = members[i]
+            prog = progs[i]
+            if k == 1 and any(v != 0 for v in lq[i]):
+                moved.add(i)
+            got = batch.members[i].round_outputs()
+            lam = batch.members[i].get_lambda()
+            for r in reps[i]:
+                say(f"[batch] round {k} member {i} {prob.name} replica {r}")
+                x, g = O.sa_round(prog, lq[i], k, r, 1, 1)
+                xb = B.unpack_bits(got["x_bits"][r:r + 1], prog.n_ext)
+                assert (xb[0] == x[0]).all(), f"round {k} member {i} replica {r}: state differs"
+                assert (got["g"][r, :prob.m] == g[0]).all()
+            # the residual sums are the sums of the per-replica residuals
+            assert (got["G"] == got["g"].astype(np.int64).sum(axis=0)).all()
+            assert got["round"] == k + 1
+            acc[i], lq[i] = O.lambda_step(prog, acc[i], [int(v) for v in got["G"][:prob.m]])
+            assert [int(v) for v in lam[:prob.m]] == lq[i], f"round {k} member {i}: multipliers"
+    assert len(moved) >= 3, moved  # round 1 ran at lambda != 0 (the QKP members)
     batch.close()

@@ -55,6 +55,7 @@ def assert_round_equal(prog, ref, got, k):
     assert (got["feasible"].astype(bool) == ref["feasible_mask"]).all(), f"round {k}: feasibility differs"
     assert [int(v) for v in got["G"]] == ref["G"], f"round {k}: residual sums differ"
     assert got["round"] == k + 1
+    assert got["lambda_saturated"] == ref["sat"], f"round {k}: saturation flags differ"
 
 
 def run_parity(prob, par, rounds, lq0=None, label=""):
@@ -72,11 +73,6 @@ def run_parity(prob, par, rounds, lq0=None, label=""):
         assert best[0] == ref["best"][0] and best[2] == ref["best"][1] and best[3] == ref["best"][2]
         assert (best[1] == ref["best"][3]).all()
     return ref, log
-
-
-def test_workload0_qkp_first_rounds(need_gpu):
-    prob, par, _ = G.workload(0, 0)
-    run_parity(prob, par, 4, label="QKP N=100 d=0.25 (workload 0)")
 
 
 def test_qkp_table1_settings_multiplier_moves(need_gpu):
@@ -140,44 +136,95 @@ def test_start_from_given_multipliers(need_gpu):
     prob = G.mkp(60, 3, G.rng_for(923, 0))
     par = G.Params(replicas=64, sweeps=50, beta=Fraction(20), eta=Fraction(1, 4), alpha=Fraction(5))
     run_parity(prob, par, 2, lq0=[512, -300, 77], label="MKP lambda_0")
+    # a start beyond the multiplier bound is clamped and flagged (constraint 1)
+    lq_max = B.pbit_plan(prob, par).lq_max
+    ref, _ = run_parity(prob, par, 2, lq0=[0, -(lq_max + 5), 3], label="MKP lambda_0 saturated")
+    assert ref["rounds"][0]["sat"] == 2
 
 
-def _spot_check_round0(prob, par, sample):
-    inst = B.Instance(prob, par)
-    inst.sample_round()
-    out = inst.round_outputs()
-    inst.update_lambda()
-    lam1 = inst.get_lambda()
-    inst.close()
-    prog = O.build_program(prob, par)
+def _check_round_properties(prog, out):
+    """Properties of one GPU round that hold for every replica: residuals,
+    profits, feasibility and the residual sums recomputed from the states."""
     x = B.unpack_bits(out["x_bits"], prog.n_ext)
-    for r in sample:
-        xo, go = O.sa_round(prog, [0] * prog.m, 0, int(r), 1, 1)
-        assert (x[r] == xo[0]).all(), f"replica {r} state differs"
-        assert (out["g"][r] == go[0]).all(), f"replica {r} residual differs"
-        pr, fe = O.score(prog, xo)
-        assert out["profit"][r] == pr[0] and bool(out["feasible"][r]) == bool(fe[0])
-    # properties over all replicas
     assert (O.residual(prog, x) == out["g"]).all()
     pr, fe = O.score(prog, x)
     assert (pr == out["profit"]).all() and (fe == out["feasible"].astype(bool)).all()
     assert [int(v) for v in out["G"]] == [int(v) for v in out["g"].astype(np.int64).sum(axis=0)]
-    _, lq = O.lambda_step(prog, [0] * prog.m, [int(v) for v in out["G"]])
-    assert [int(v) for v in lam1] == lq
+    return x, pr, fe
 
 
-def test_full_size_workload2_round0(need_gpu):
-    """QKP N=300 d=1, 4096 replicas x 5000 sweeps: sampled replicas replayed by the oracle."""
+def _spot_check_rounds(prob, par, sample, rounds=1, lq0=None):
+    """Runs `rounds` full-size rounds on the GPU.  Every round: sampled replicas
+    replayed alone by the oracle under the multipliers the GPU used (rounds
+    after the first run at lambda != 0, which exercises the lambda-dependent
+    site constants), properties over all replicas, the multiplier step checked
+    against the oracle's step from the GPU's residual sums, and the best record
+    against the oracle's rule applied to the GPU's (checked) round results."""
+    inst = B.Instance(prob, par)
+    prog = O.build_program(prob, par)
+    lq = [0] * prog.m if lq0 is None else list(lq0)
+    if lq0 is not None:
+        inst.set_lambda(lq)
+    acc = [v << 24 for v in lq]
+    used = []
+    best = None
+    for k in range(rounds):
+        used.append(list(lq))
+        assert [int(v) for v in inst.get_lambda()] == lq
+        inst.sample_round()
+        out = inst.round_outputs()
+        inst.update_lambda()
+        lam = inst.get_lambda()
+        x, pr, fe = _check_round_properties(prog, out)
+        for r in sample:
+            say(f"[parity] round {k} replica {r} lambda_q {lq[:4]}")
+            xo, go = O.sa_round(prog, lq, k, int(r), 1, 1)
+            assert (x[r] == xo[0]).all(), f"round {k} replica {r}: state differs"
+            assert (out["g"][r] == go[0]).all(), f"round {k} replica {r}: residual differs"
+        best = O.best_update(best, k, pr, fe, x[:, :prog.n])
+        acc, lq = O.lambda_step(prog, acc, [int(v) for v in out["G"]])
+        assert [int(v) for v in lam] == lq, f"round {k}: multiplier step differs"
+        assert out["round"] == k + 1
+    got = inst.best_feasible()
+    inst.close()
+    if best is None:
+        assert got is None
+    else:
+        assert got is not None and (got[0], got[2], got[3]) == best[:3]
+        assert (got[1] == best[3]).all()
+    return used
+
+
+def test_full_size_workload2_two_rounds(need_gpu):
+    """QKP N=300 d=1, 4096 replicas x 5000 sweeps, with Table 1's QKP step eta = 20
+    so that round 1 runs at lambda != 0: sampled replicas of both rounds replayed
+    by the oracle."""
     prob, par, _ = G.workload(2, 0)
-    say("[parity] workload 2 full size, round 0")
-    _spot_check_round0(prob, par, [0, 1, 63, 64, 2047, 4095])
+    par.eta = Fraction(20)
+    say("[parity] workload 2 full size, two rounds, eta 20")
+    used = _spot_check_rounds(prob, par, [0, 1, 63, 64, 2047, 4095], rounds=2)
+    assert any(v != 0 for v in used[1])
 
 
-def test_full_size_workload1_round0(need_gpu):
-    """MKP N=250 M=10, 1024 replicas x 2000 sweeps: sampled replicas replayed by the oracle."""
+def test_full_size_workload1_two_rounds(need_gpu):
+    """MKP N=250 M=10, 1024 replicas x 2000 sweeps (Table 1's MKP step 0.05),
+    started from lambda_n = 1 + k/4 for constraint k so that both rounds run at
+    lambda != 0 (one step of 0.05 may not move lambda on its 2^-8 grid):
+    sampled replicas of rounds 0 and 1 replayed by the oracle."""
     prob, par, _ = G.workload(1, 0)
-    say("[parity] workload 1 full size, round 0")
-    _spot_check_round0(prob, par, [0, 5, 511, 1023])
+    say("[parity] workload 1 full size, two rounds")
+    lq0 = [256 + 64 * k for k in range(prob.m)]
+    used = _spot_check_rounds(prob, par, [0, 5, 511, 1023], rounds=2, lq0=lq0)
+    assert used[0] == lq0 and any(v != 0 for v in used[1])
+
+
+def test_workload0_all_rounds(need_gpu):
+    """QKP N=100 d=0.25 as specified (64 replicas, 1000 sweeps, 50 rounds): every
+    round, every replica and every multiplier against the oracle's whole loop."""
+    prob, par, K = G.workload(0, 0)
+    assert K == 50
+    ref, _ = run_parity(prob, par, K, label="QKP N=100 d=0.25 (workload 0), all rounds")
+    assert any(v != 0 for v in ref["lq"])
 
 
 @pytest.mark.parametrize("case", ["qkp97", "mkp100x5", "mkp100x30", "mkp120x12wide"])
@@ -268,7 +315,7 @@ def test_maximum_shapes(need_gpu):
     par = G.Params(replicas=128, sweeps=3, beta=Fraction(50), eta=Fraction(1, 2), alpha=Fraction(5))
     assert 1900 < B.pbit_plan(big, par).n_ext <= 2048
     say("[parity] MKP n=1400 M=32, sampled replicas")
-    _spot_check_round0(big, par, [0, 77, 127])
+    _spot_check_rounds(big, par, [0, 77, 127], rounds=2)
 
 
 def test_tiling_choices_are_validated(need_gpu):
