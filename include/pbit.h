@@ -130,6 +130,29 @@ typedef struct pbit_instance pbit_instance; /* opaque */
 pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *par, void *dev_ws,
                                  size_t ws_bytes, pbit_stream stream, pbit_instance **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): pbit_create_instance
+ * with the workspace taken from a static device array of the library
+ * (pbit_static_workspace_bytes() = 16 MiB per device, resident from the first
+ * such call on a device until the process ends) instead of a caller buffer.
+ * Allocates no device memory and calls no allocating library routine; the
+ * host-side handle is created as for pbit_create_instance.  Every other entry
+ * point works on the returned instance unchanged; pbit_round_outputs still
+ * writes into the caller's buffer.
+ * One device has one static workspace: while an instance made by this call is
+ * live on a device, a second call on that device returns PBIT_ESTATE, and
+ * pbit_destroy_instance releases it.  The array keeps the last instance's
+ * contents; creation overwrites every byte the kernels read before writing.
+ * Work of a destroyed static instance that is still queued on another stream
+ * races with the next static instance on that device: order the two streams.
+ * Errors: as pbit_create_instance, and PBIT_EWORKSPACE when the instance needs
+ * more than pbit_static_workspace_bytes(), PBIT_ESTATE as above. */
+pbit_status pbit_create_instance_static(const pbit_problem *prob, const pbit_params *par, pbit_stream stream,
+                                        pbit_instance **out);
+
+/* Size of the static per-device workspace used by pbit_create_instance_static. */
+size_t pbit_static_workspace_bytes(void);
+
 /* One annealing run of every replica (Sec. III-B; Algorithm 1 "minimise L_k"):
  * each replica starts at x = 0 and performs T sequential Gibbs sweeps of the
  * p-bit update (Eq. Ii_eq, Eq. mi_eq) with beta rising linearly; its last

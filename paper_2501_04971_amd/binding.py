@@ -63,6 +63,9 @@ EXPORTS = {
     "pbit_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_create_instance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_create_instance_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p]),
+    "pbit_static_workspace_bytes": (ctypes.c_size_t, []),
     "pbit_sample_round": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_update_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_set_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -195,6 +198,19 @@ def pbit_create_instance(prob: Problem, par: Params, workspace, stream=None) -> 
     return int(handle.value)
 
 
+def pbit_create_instance_static(prob: Problem, par: Params, stream=None) -> int:
+    """As pbit_create_instance, with the library's static per-device workspace."""
+    mp = _Marshalled(prob, par)
+    handle = ctypes.c_void_p()
+    _check(lib().pbit_create_instance_static(ctypes.byref(mp.problem), ctypes.byref(mp.params),
+                                             _stream_handle(stream), ctypes.byref(handle)))
+    return int(handle.value)
+
+
+def pbit_static_workspace_bytes() -> int:
+    return int(lib().pbit_static_workspace_bytes())
+
+
 def pbit_sample_round(inst: int, stream=None) -> None:
     _check(lib().pbit_sample_round(inst, _stream_handle(stream)))
 
@@ -310,11 +326,15 @@ def pbit_destroy_batch(batch: int) -> None:
 class Instance:
     """One compiled instance with its torch-owned workspace on the current device."""
 
-    def __init__(self, prob: Problem, par: Params, stream=None, _member=None):
+    def __init__(self, prob: Problem, par: Params, stream=None, _member=None, static_workspace=False):
         import torch
         self.problem, self.params, self.stream = prob, par, stream
         self.owned = _member is None
-        if self.owned:
+        if self.owned and static_workspace:
+            self.info = pbit_plan(prob, par)
+            self.workspace = None
+            self.handle = pbit_create_instance_static(prob, par, stream)
+        elif self.owned:
             self.info = pbit_plan(prob, par)
             # torch's caching allocator hands out blocks aligned to at least 512 bytes
             self.workspace = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device="cuda")

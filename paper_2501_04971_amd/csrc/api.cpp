@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -542,6 +543,7 @@ struct pbit_instance {
     int cus = 256;
     bool broken = false;
     bool member = false;  // owned by a batch
+    int static_dev = -1;  // device whose static workspace this instance holds (-1: caller's workspace)
 };
 
 struct pbit_batch {
@@ -878,6 +880,21 @@ pbit_status check_net_shape(int sets, int rows)
     return PBIT_OK;
 }
 
+// Workspace of allocation-free instances (pbit_create_instance_static): one
+// array per device, resident until the process ends.  Host code never passes
+// the symbol itself to a kernel or copy: it takes the device address of each
+// device's copy with hipGetSymbolAddress once, with that device current.
+constexpr size_t kStaticWsBytes = (size_t)16 << 20;
+constexpr int kStaticMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+struct StaticSlot {
+    void *ptr = nullptr;  // device address of this device's scratch array
+    bool held = false;    // a live instance uses it
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kStaticMaxDevices];
+
 }  // namespace
 
 extern "C" {
@@ -914,6 +931,40 @@ pbit_status pbit_create_instance(const pbit_problem *prob, const pbit_params *pa
                                  size_t ws_bytes, pbit_stream stream, pbit_instance **out)
 {
     return create_impl(prob, par, dev_ws, ws_bytes, stream, out);
+}
+
+size_t pbit_static_workspace_bytes(void) { return kStaticWsBytes; }
+
+pbit_status pbit_create_instance_static(const pbit_problem *prob, const pbit_params *par, pbit_stream stream,
+                                        pbit_instance **out)
+{
+    if (!out) return fail(PBIT_EINVAL, "null output handle");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PBIT_EDEVICE, std::string("device query failed: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(PBIT_EINVAL, "device index beyond the static workspace table");
+    Plan P;
+    pbit_status st = make_plan(prob, par, P);
+    if (st != PBIT_OK) return st;
+    if (P.L.total > kStaticWsBytes)
+        return fail(PBIT_EWORKSPACE, "instance needs " + std::to_string(P.L.total) +
+                                         " workspace bytes, more than the static workspace of " +
+                                         std::to_string(kStaticWsBytes) + "; use pbit_create_instance");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticSlot &slot = g_static[dev];
+    if (slot.held) return fail(PBIT_ESTATE, "the static workspace of this device is held by a live instance");
+    if (!slot.ptr) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PBIT_EDEVICE, std::string("static workspace address lookup failed: ") + hipGetErrorString(e));
+        slot.ptr = ptr;
+    }
+    st = create_impl(prob, par, slot.ptr, kStaticWsBytes, stream, out);
+    if (st != PBIT_OK) return st;
+    (*out)->static_dev = dev;
+    slot.held = true;
+    return PBIT_OK;
 }
 
 pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
@@ -1049,6 +1100,10 @@ pbit_status pbit_destroy_instance(pbit_instance *inst)
 {
     if (!inst) return fail(PBIT_EINVAL, "null instance");
     if (inst->member) return fail(PBIT_EINVAL, "instance is a batch member; destroy the batch");
+    if (inst->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static[inst->static_dev].held = false;
+    }
     delete inst;
     return PBIT_OK;
 }
