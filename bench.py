@@ -41,16 +41,50 @@ SIMDS = 256 * 4
 MFMA_I8_PEAK = 5.0e15
 LDS_PEAK = 256 * 128 * 2.4e9
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2)
-# and WRITE_SIZE (x1) passes (calibrated on a 256 MiB copy); valid for the
-# kernel build they were taken on, keyed by kernel and workload.
-MEASURED_TRAFFIC = {("sweep_quad_pc<10, 3>", 2): (863.9375 * 2 + 224) * 1024}
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2501_04971_amd", "csrc")
 
-# LDS-pipe and matrix-core activity of the same kernel builds from rocprofv3 SQ
-# counters (SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, SQ_VALU_MFMA_BUSY_CYCLES),
-# as fractions of the cycles of the CUs the launch occupies.
-MEASURED_UTIL = {("sweep_quad_pc<10, 3>", 2): {"lds_pipe_active": 0.260, "lds_bank_conflict_share": 0.41,
-                                               "mfma_busy": 0.099}}
+
+def kernel_source_hash() -> str:
+    """sha256 over the library's kernel sources (every .h and .hip file, in name
+    order): a counter figure recorded for another build of the kernels does not
+    describe this one."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SOURCES)):
+        if name.endswith((".h", ".hip")):
+            h.update(name.encode())
+            with open(os.path.join(KERNEL_SOURCES, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_counters(kernel: str, workload: int):
+    """Counter figures of this kernel build from the rocprofv3 summaries under
+    profiles/ (a `bench-counters` block naming the kernel, the workload and the
+    source hash they were taken on), or None when no summary matches the
+    current sources."""
+    import glob
+    want = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        text = open(path).read()
+        start = text.find("<!-- bench-counters")
+        if start < 0:
+            continue
+        block = text[start:text.find("-->", start)]
+        rec = {}
+        for line in block.splitlines()[1:]:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+        if rec.get("kernel") == kernel and rec.get("workload") == str(workload) and rec.get("sources") == want:
+            out = {"file": os.path.relpath(path, ROOT)}
+            for k, v in rec.items():
+                if k not in ("kernel", "workload", "sources"):
+                    out[k] = float(v)
+            return out
+    return None
+
 
 WORKLOAD_NAMES = {0: "QKP N=100 d=0.25", 1: "MKP N=250 M=10", 2: "QKP N=300 d=1.0",
                   3: "mixed batch: 256 QKP + 256 MKP, 256 replicas each"}
@@ -82,11 +116,33 @@ def quad_secondary(info, updates, seconds):
                     "frac": lds_bytes / seconds / LDS_PEAK}}
 
 
+def host_cpu():
+    """(logical CPUs of the machine, CPUs this process may run on, CPU model)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return os.cpu_count() or 1, usable, model
+
+
+# A one-GPU box grants its process a share of 16 host CPUs whatever the machine
+# has; the CPU leg uses every CPU it may run on, up to that share.
+HOST_CPU_SHARE = 16
+
+
 def cpu_baseline(members, seconds_target: float = 15.0):
     """The plain CPU oracle on a bounded sample of the same workload: round 0
-    of a few replicas (full sweep count) of the first member(s)."""
+    of a few replicas (full sweep count) of the first member(s), one thread
+    per usable host CPU."""
     from oracle import oracle as O
-    threads = max(1, min(16, os.cpu_count() or 1))
+    nproc, usable, model = host_cpu()
+    threads = max(1, min(HOST_CPU_SHARE, usable))
     t_all, visits_all, desc = 0.0, 0, []
     for prob, par in members:
         prog = O.build_program(prob, par)
@@ -102,7 +158,9 @@ def cpu_baseline(members, seconds_target: float = 15.0):
         visits_all += reps * prog.n_ext * prog.T
         desc.append(f"{reps} replicas x {prog.T} sweeps x {prog.n_ext} spins")
     return {"value": visits_all / t_all, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"round 0 of: {'; '.join(desc)} ({visits_all:.3g} updates, {t_all:.1f} s)"}
+            "sample": f"round 0 of: {'; '.join(desc)} ({visits_all:.3g} updates, {t_all:.1f} s)",
+            "host": {"nproc": nproc, "usable_cpus": usable, "model": model,
+                     "threads_rule": f"min(usable CPUs, {HOST_CPU_SHARE})"}}
 
 
 def learned_start_summary(count: int = 64, rounds: int = 150):
@@ -233,6 +291,9 @@ def main() -> int:
                "replicas": par.replicas, "sweeps_per_round": par.sweeps,
                "updates_per_step": updates_per_step, "parallelism": "one GPU, replicas across lanes"}
     runner.close()
+    # counters are not measured by this run: they are the rocprofv3 figures
+    # recorded under profiles/ for these exact kernel sources, if any
+    counters = recorded_counters(kernel, args.workload)
 
     out = {
         "metric": "p-bit spin updates/s",
@@ -255,14 +316,14 @@ def main() -> int:
             "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (32-bit integer)",
             "frac": achieved / ALU_PEAK_OPS,
-            "traffic": None if batch else MEASURED_TRAFFIC.get((kernel, args.workload)),
+            "traffic": None if counters is None else counters.get("traffic_bytes"),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "ops_per_update": None if batch else alu_ops_per_update(info.m),
             "launch_ms": launch_ms,
             "waves": waves,
             "frac_of_occupied_simds": achieved / (ALU_PEAK_OPS * min(1.0, waves / SIMDS)),
             "secondary": secondary,
-            "rocprof_utilization": None if batch else MEASURED_UTIL.get((kernel, args.workload)),
+            "recorded_counters": counters,
         },
         "wall_s": wall,
         "best_feasible_profit": None if best is None else best[0],

@@ -176,18 +176,29 @@ pbit_status pbit_update_lambda(pbit_instance *inst, pbit_stream stream);
  * Values are clamped to +-lq_max.  Copy ordered on stream. */
 pbit_status pbit_set_lambda(pbit_instance *inst, const int32_t *lambda_q, pbit_stream stream);
 
-/* Copies the current lambda_q (m values) to host memory; synchronises stream. */
+/* Copies the current lambda_q (m values; lambda_n = lambda_q / 256, the
+ * multipliers of Eq. Lagrange_energy that Algorithm 1 carries from one
+ * iteration to the next) to host memory; synchronises stream.
+ * Errors: PBIT_EINVAL (null pointer), PBIT_ESTATE, PBIT_EDEVICE. */
 pbit_status pbit_get_lambda(pbit_instance *inst, int32_t *lambda_q, pbit_stream stream);
 
-/* Best feasible sample so far: profit, the n original bits (host bytes 0/1),
- * the round and replica it came from.  Synchronises stream.  Returns
- * PBIT_NOFEAS (outputs untouched) when no feasible sample exists yet.
- * Any pointer may be NULL. */
+/* Best feasible sample so far: Algorithm 1 keeps every feasible sample of
+ * every iteration and returns the one of lowest objective (here: largest
+ * profit; ties to the earliest round, then the lowest replica), scored on the
+ * original bits as in Sec. IV-A.  Outputs: profit, the n original bits (host
+ * bytes 0/1), the round and replica it came from.  Synchronises stream.
+ * Returns PBIT_NOFEAS (outputs untouched) when no feasible sample exists yet.
+ * Any pointer may be NULL.  Errors: PBIT_ESTATE, PBIT_EDEVICE. */
 pbit_status pbit_best_feasible(pbit_instance *inst, int64_t *profit, uint8_t *x, int32_t *round,
                                int32_t *replica, pbit_stream stream);
 
 /* Copies the last round's per-replica results into dev_out (caller-owned
- * device memory of at least pbit_plan_info.out_bytes), ordered on stream:
+ * device memory of at least pbit_plan_info.out_bytes), ordered on stream.
+ * These are the quantities of one iteration of Algorithm 1: the samples x_k,
+ * their constraint residuals g(x_k) (whose replica sum drives the multiplier
+ * step), their objective and feasibility (Sec. IV-A), and the multipliers for
+ * the next iteration.  Errors: PBIT_EWORKSPACE (dev_out null or too small),
+ * PBIT_ESTATE, PBIT_EDEVICE.  Layout (byte offsets from pbit_plan_info):
  *   out_x        uint32 [R][words]  final states, bit i of word i/32 = spin i
  *   out_g        int32  [R][m]      residuals A_ext x - b
  *   out_profit   int64  [R]         profit of the original bits
