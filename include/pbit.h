@@ -82,7 +82,14 @@ typedef struct {
  *  alpha        the rule's constant.
  *  seed         Philox4x32-10 key.
  *  instance_id  last Philox counter word.
- *  fixed_beta   nonzero: every sweep runs at beta_max (test mode). */
+ *  fixed_beta   nonzero: every sweep runs at beta_max (test mode).
+ *  eta_decay_rounds  H >= 0: the step after round k (0-based) is
+ *               eta_k = eta H / (H + k), a diminishing step (sum eta_k diverges,
+ *               sum eta_k^2 converges: the step-size conditions under which the
+ *               surrogate subgradient ascent of Sec. III-A converges); 0 keeps
+ *               eta constant as in Algorithm 1.  At most 2^20; k is capped where
+ *               the step's 64-bit denominator would overflow (beyond 10^9
+ *               rounds for every instance the bounds admit). */
 typedef struct {
     int32_t replicas, sweeps;
     int32_t beta_num, beta_den;
@@ -92,6 +99,7 @@ typedef struct {
     uint64_t seed;
     uint32_t instance_id;
     int32_t fixed_beta;
+    int32_t eta_decay_rounds;
 } pbit_params;
 
 /* Host-side description of a compiled instance (no device needed). */
@@ -296,11 +304,16 @@ pbit_status pbit_batch_shape(const pbit_batch *batch, int32_t *items, int32_t *b
  * pbit_net_to_lambda.  Asynchronous on stream. */
 pbit_status pbit_batch_set_lambdas(pbit_batch *batch, const int32_t *lambda_q, pbit_stream stream);
 
-/* Writes one 160-byte record per member to dev_out (device memory), ordered
+/* Writes one 176-byte record per member to dev_out (device memory), ordered
  * on stream: int64 best feasible profit; int32 its round, 1 if any feasible
  * sample exists, rounds done, feasible samples in the last round, the
  * multiplier saturation mask (out_sat of pbit_round_outputs), one zero
- * word; int32 lambda_q[32] (zero beyond m). */
+ * word; int32 lambda_q[32] (zero beyond m); int64 sum of the profits of the
+ * last round's feasible samples; int64 sum over the last round's samples of
+ * |g|^2 (squared residuals with slack, the penalty term of Eq.
+ * penalty_energy in data units).  Together with the feasible count these give
+ * the mean objective of the feasible samples that the accuracy metric of
+ * Sec. IV-A averages, without copying every sample to the host. */
 pbit_status pbit_batch_snapshot(pbit_batch *batch, void *dev_out, pbit_stream stream);
 
 /* Releases the batch, its members and its graph.  Does not synchronise. */

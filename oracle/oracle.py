@@ -115,6 +115,8 @@ class Program:
     R: int
     seed: int
     inst: int
+    eta_decay: int = 0     # H of the diminishing step eta H / (H + k); 0: constant
+    eta_kcap: int = 0      # largest k entering H + k
 
     def beta_values(self) -> list:
         """beta_t implied by the grid (for documentation and tests)."""
@@ -216,9 +218,22 @@ def build_program(prob: Problem, par: Params) -> Program:
     if lq_max < 256:
         raise OracleRangeError("multiplier range below 1.0")
 
+    # diminishing multiplier step eta H / (H + k) (Sec. III-A's surrogate
+    # subgradient ascent converges under such steps); k is capped where the
+    # exact step's denominator eta_den R s_g (H + k) would reach 2^62
+    H = int(getattr(par, "eta_decay", 0))
+    if H < 0 or H > (1 << 20):
+        raise ValueError("eta_decay must lie in [0, 2^20]")
+    kcap = 0
+    if H > 0:
+        lam_den = Fraction(par.eta).denominator * int(par.replicas) * s_g
+        kcap = min(((1 << 62) - 1) // lam_den - H, (1 << 31) - 1)
+        if kcap < 1:
+            raise OracleRangeError("diminishing step exceeds 64-bit bounds")
+
     return Program(prob.kind, n, m, n_ext, Q, slack, W, h, A, b0.copy(), s_f, s_g, D, pq, T, S,
                    B, lq_max, Fraction(par.eta), int(par.replicas), int(par.seed),
-                   int(par.instance_id))
+                   int(par.instance_id), H, kcap)
 
 
 # ---------------------------------------------------------------------------
@@ -266,13 +281,23 @@ def index_of(prog: Program, Z: int, t: int) -> int:
 # ---------------------------------------------------------------------------
 # multiplier update (Algorithm 1, with the replica mean of g)
 
-def lambda_step(prog: Program, lam_acc: list, G: list, R: int | None = None):
-    """lam_acc on a 2^-32 grid of lambda_n; returns (new lam_acc, lq on 2^-8 grid)."""
+def step_size(prog: Program, k: int) -> Fraction:
+    """eta of the step after round k: constant (Algorithm 1), or eta H / (H + k)."""
+    if prog.eta_decay == 0:
+        return prog.eta
+    k = max(0, min(int(k), prog.eta_kcap))
+    return prog.eta * Fraction(prog.eta_decay, prog.eta_decay + k)
+
+
+def lambda_step(prog: Program, lam_acc: list, G: list, R: int | None = None, k: int = 0):
+    """lam_acc on a 2^-32 grid of lambda_n; returns (new lam_acc, lq on 2^-8 grid).
+    k is the index of the round whose residual sums G are (it sets the step size)."""
     R = prog.R if R is None else R
     cap = prog.lq_max << 24
+    eta = step_size(prog, k)
     new_acc, lq = [], []
     for acc, Gk in zip(lam_acc, G):
-        delta = round_half_away(Fraction(1 << 32) * prog.eta * int(Gk) / (R * prog.s_g))
+        delta = round_half_away(Fraction(1 << 32) * eta * int(Gk) / (R * prog.s_g))
         acc = max(-cap, min(cap, int(acc) + delta))
         new_acc.append(acc)
         lq.append(round_half_away(Fraction(acc, 1 << 24)))
@@ -427,6 +452,6 @@ def saim(prob: Problem, par: Params, rounds: int, lq0=None, nthreads: int | None
         if keep_states:
             entry.update(x=x, g=g, profit=profit, feasible_mask=feas)
         log.append(entry)
-        acc, lq = lambda_step(prog, acc, G)
+        acc, lq = lambda_step(prog, acc, G, k=k)
         sat = saturation_mask(acc, cap, sat)
     return {"program": prog, "rounds": log, "best": best, "lq": lq, "acc": acc, "sat": sat}

@@ -41,7 +41,8 @@ class pbit_params(ctypes.Structure):
                 ("eta_num", ctypes.c_int32), ("eta_den", ctypes.c_int32),
                 ("p_q", ctypes.c_int32), ("alpha_num", ctypes.c_int32),
                 ("alpha_den", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("instance_id", ctypes.c_uint32), ("fixed_beta", ctypes.c_int32)]
+                ("instance_id", ctypes.c_uint32), ("fixed_beta", ctypes.c_int32),
+                ("eta_decay_rounds", ctypes.c_int32)]
 
 
 class pbit_plan_info(ctypes.Structure):
@@ -113,7 +114,7 @@ EXPORTS = {
                                           ctypes.c_void_p, ctypes.c_void_p]),
 }
 
-SNAPSHOT_BYTES = 160
+SNAPSHOT_BYTES = 176
 MAX_M = 32
 
 _LIB = None
@@ -125,6 +126,10 @@ def lib() -> ctypes.CDLL:
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paper_2501_04971_amd.build first")
+        # torch brings its own HIP runtime; loading it first makes the library
+        # bind to that same runtime instead of a second copy (two runtimes in
+        # one process do not see each other's devices)
+        import torch  # noqa: F401
         so = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in EXPORTS.items():
             fn = getattr(so, name)
@@ -161,7 +166,8 @@ class _Marshalled:
         self.params = pbit_params(int(par.replicas), int(par.sweeps), bn, bd, en, ed,
                                   -1 if par.p_q is None else int(par.p_q), an, ad,
                                   int(par.seed) & ((1 << 64) - 1),
-                                  int(par.instance_id) & 0xFFFFFFFF, 1 if par.fixed_beta else 0)
+                                  int(par.instance_id) & 0xFFFFFFFF, 1 if par.fixed_beta else 0,
+                                  int(par.eta_decay))
 
 
 def pbit_plan(prob: Problem, par: Params) -> pbit_plan_info:
@@ -402,7 +408,7 @@ def pbit_batch_set_lambdas(batch: int, lambda_q, stream=None) -> None:
 
 
 def pbit_batch_snapshot(batch: int, out, stream=None) -> None:
-    """out: uint8 CUDA tensor of count * 160 bytes."""
+    """out: uint8 CUDA tensor of count * SNAPSHOT_BYTES bytes."""
     _check(lib().pbit_batch_snapshot(batch, out.data_ptr(), _stream_handle(stream)))
 
 
@@ -414,7 +420,9 @@ def decode_snapshot(raw: np.ndarray, count: int) -> dict:
             "best_round": head[:, 0], "has_feasible": head[:, 1].astype(bool),
             "rounds": head[:, 2], "feasible_last": head[:, 3],
             "lambda_saturated": head[:, 4].view(np.uint32),
-            "lambda_q": r[:, 32:].copy().view(np.int32).reshape(count, MAX_M)}
+            "lambda_q": r[:, 32:160].copy().view(np.int32).reshape(count, MAX_M),
+            "feasible_profit_sum": r[:, 160:168].copy().view(np.int64).reshape(count),
+            "residual_sq_sum": r[:, 168:176].copy().view(np.int64).reshape(count)}
 
 
 # ---- learned starting multipliers -------------------------------------------
@@ -503,7 +511,7 @@ class Batch:
         pbit_batch_set_lambdas(self.handle, lambda_q, self.stream)
 
     def snapshot(self, out):
-        """Queues the per-member records into out (uint8 CUDA tensor, count * 160 bytes)."""
+        """Queues the per-member records into out (uint8 CUDA tensor, count * SNAPSHOT_BYTES)."""
         pbit_batch_snapshot(self.handle, out, self.stream)
 
     def shape(self):

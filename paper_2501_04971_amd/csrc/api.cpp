@@ -154,6 +154,7 @@ struct Plan {
     int32_t zsh = 0, ish = 0, hclo = 0, hchi = 0;
     int64_t irnd = 0;
     int64_t sfsg = 0, eta_num = 0, lam_den = 1;
+    int32_t eta_h = 0, eta_kcap = 0;
     int n_rec = 0;                 // per-site records (padding included)
     std::vector<int64_t> site;     // [n_rec][4]: K0, K1 (filled on the device), c, meta
     uint64_t seed = 0;
@@ -341,6 +342,17 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
         return fail(PBIT_ERANGE, "multiplier step too large");
     P.eta_num = par->eta_num;
     P.lam_den = (int64_t)lam_den;
+    // diminishing step eta H / (H + k): numerator eta_num G H, denominator lam_den (H + k)
+    if (par->eta_decay_rounds < 0 || par->eta_decay_rounds > (1 << 20))
+        return fail(PBIT_EINVAL, "eta_decay_rounds must lie in [0, 2^20]");
+    P.eta_h = par->eta_decay_rounds;
+    if (P.eta_h > 0) {
+        if ((i128)par->eta_num * P.R * gmax * P.eta_h >= ((i128)1 << 62))
+            return fail(PBIT_ERANGE, "diminishing multiplier step exceeds 64-bit bounds");
+        const i128 kc = (((i128)1 << 62) - 1) / lam_den - P.eta_h;
+        if (kc < 1) return fail(PBIT_ERANGE, "diminishing multiplier step exceeds 64-bit bounds");
+        P.eta_kcap = (int32_t)std::min<i128>(kc, (i128)INT32_MAX);
+    }
 
     // beta grid: B_t = round(2^S beta_t / (2 s_f s_g^2)), S the smallest giving B_{T-1} >= 2^30
     const u128 den = (u128)2 * P.s_f * (u128)sg2;
@@ -684,6 +696,8 @@ pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *
     d.sfsg = P.sfsg;
     d.lq_max = P.lq_max;
     d.eta_num = P.eta_num;
+    d.eta_h = P.eta_h;
+    d.eta_kcap = P.eta_kcap;
     d.lam_den = P.lam_den;
     d.seed_lo = (uint32_t)P.seed;
     d.seed_hi = (uint32_t)(P.seed >> 32);

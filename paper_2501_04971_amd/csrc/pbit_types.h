@@ -12,7 +12,7 @@ constexpr int kMaxM = 32;                   // constraints per instance
 constexpr int kMaxQuadBlocks = 11;          // quadratic kernel: n_ext <= 352
 constexpr int kMaxWords = 64;               // linear kernel: n_ext <= 2048
 constexpr int kWave = 64;
-constexpr int kSnapshotBytes = 160;  // per-member record of batch snapshots
+constexpr int kSnapshotBytes = 176;  // per-member record of batch snapshots
 constexpr int kBatchSplit = 0x100;   // work-item code flag: split (1 + 3 waves, 64 replicas) linear tile
 // producer/consumer kernels: double-buffered threshold ring (32 sites x 64 lanes)
 constexpr size_t kRingBytes = 2 * 32 * 64 * 8;
@@ -59,6 +59,8 @@ struct DevInstance {
     int64_t eta_num;
     int64_t lam_den;          // eta_den * R * s_g
     uint32_t seed_lo, seed_hi, inst_id;
+    int32_t eta_h;            // diminishing step eta H / (H + k); 0: constant eta
+    int32_t eta_kcap;         // largest k used in H + k (keeps lam_den (H + k) < 2^62)
     int32_t pad0;
 };
 

@@ -119,7 +119,17 @@ __device__ __forceinline__ void lambda_update_body(const DevInstance &d, int mod
     if (tid < d.m) {
         int64_t acc = d.lam_acc[tid];
         const int64_t cap = d.lq_max << 24;
-        if (mode == 1) acc += round_scaled_div(d.eta_num * d.G[tid], d.lam_den);
+        if (mode == 1) {
+            // step after round k = round_k - 1: eta, or eta H / (H + k)
+            int64_t num = d.eta_num * d.G[tid], den = d.lam_den;
+            if (d.eta_h > 0) {
+                int64_t k = (int64_t)d.round_k[0] - 1;
+                k = k < 0 ? 0 : (k > d.eta_kcap ? (int64_t)d.eta_kcap : k);
+                num *= d.eta_h;
+                den *= d.eta_h + k;
+            }
+            acc += round_scaled_div(num, den);
+        }
         if (mode == 2) acc = (int64_t)vals[tid] * (1 << 24);
         acc = acc > cap ? cap : acc;
         acc = acc < -cap ? -cap : acc;
@@ -195,6 +205,31 @@ __global__ __launch_bounds__(64) void batch_snapshot(const DevInstance *insts, u
         h[5] = 0;
     }
     if (tid < kMaxM) reinterpret_cast<int32_t *>(rec + 32)[tid] = tid < d.m ? d.lam_q[tid] : 0;
+    // sums over the last round's samples: profits of the feasible ones, |g|^2
+    // of all (fixed order: lane-strided partial sums, then a tree in LDS)
+    __shared__ int64_t part[2][64];
+    int64_t sp = 0, sq = 0;
+    for (int r = tid; r < d.R; r += 64) {
+        if (d.rfeas[r]) sp += d.rprofit[r];
+        for (int k = 0; k < d.m; ++k) {
+            const int64_t g = d.rg[(int64_t)r * d.m + k];
+            sq += g * g;
+        }
+    }
+    part[0][tid] = sp;
+    part[1][tid] = sq;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (tid < w) {
+            part[0][tid] += part[0][tid + w];
+            part[1][tid] += part[1][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        reinterpret_cast<int64_t *>(rec + 160)[0] = part[0][0];
+        reinterpret_cast<int64_t *>(rec + 160)[1] = part[1][0];
+    }
 }
 
 hipError_t launch_lambda_set_batch(const DevInstance *insts, int count, const int32_t *values, hipStream_t stream)

@@ -70,6 +70,7 @@ class Params:
     seed         Philox key
     instance_id  last Philox counter word (tells instances of a batch apart)
     fixed_beta   hold beta at beta_max for every sweep (test mode)
+    eta_decay    H: diminishing step eta H / (H + k) after round k; 0 = constant
     """
 
     replicas: int = 64
@@ -81,6 +82,7 @@ class Params:
     seed: int = 0
     instance_id: int = 0
     fixed_beta: bool = False
+    eta_decay: int = 0
 
 
 def rng_for(family: int, index: int) -> np.random.Generator:

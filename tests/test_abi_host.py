@@ -152,3 +152,12 @@ def test_round_output_layout_has_the_saturation_word(lib):
     info = B.pbit_plan(prob, par)
     assert info.out_round < info.out_sat < info.out_bytes
     assert info.out_sat % 256 == 0
+
+
+def test_diminishing_step_settings_are_validated(lib):
+    """eta_decay_rounds outside [0, 2^20] is refused; inside it plans."""
+    prob, par, _ = G.workload(0, 0)
+    for bad in (-1, (1 << 20) + 1):
+        _expect(B.PBIT_EINVAL, prob, G.Params(replicas=64, sweeps=10, eta_decay=bad))
+    for ok in (0, 1, 1 << 20):
+        B.pbit_plan(prob, G.Params(replicas=64, sweeps=10, eta_decay=ok))

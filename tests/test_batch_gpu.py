@@ -182,7 +182,7 @@ def test_batch_workload3_sampled(need_gpu):
             # the residual sums are the sums of the per-replica residuals
             assert (got["G"] == got["g"].astype(np.int64).sum(axis=0)).all()
             assert got["round"] == k + 1
-            acc[i], lq[i] = O.lambda_step(prog, acc[i], [int(v) for v in got["G"][:prob.m]])
+            acc[i], lq[i] = O.lambda_step(prog, acc[i], [int(v) for v in got["G"][:prob.m]], k=k)
             assert [int(v) for v in lam[:prob.m]] == lq[i], f"round {k} member {i}: multipliers"
     assert len(moved) >= 3, moved  # round 1 ran at lambda != 0 (the QKP members)
     batch.close()

@@ -172,6 +172,9 @@ def test_lambda_mapping_and_batch_start(need_gpu, packed):
         ref = O.saim(p, q, 2, lq0=lq0, nthreads=8)
         assert [int(v) for v in rec["lambda_q"][i, :p.m]] == ref["lq"], f"member {i}"
         assert rec["rounds"][i] == 2
+        last = ref["rounds"][-1]
+        assert rec["feasible_profit_sum"][i] == int(last["profit"][last["feasible_mask"]].sum())
+        assert rec["residual_sq_sum"][i] == int((last["g"].astype(np.int64) ** 2).sum())
         if ref["best"] is None:
             assert not rec["has_feasible"][i]
         else:

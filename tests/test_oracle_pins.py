@@ -161,6 +161,50 @@ def test_lambda_step_exact_rationals():
             acc = new_acc
 
 
+def test_diminishing_step_literal_values():
+    """eta_k = eta H / (H + k): with eta = s_g / 2^32 and H = 4 the accumulator
+    step for G = 30 after rounds k = 0..5 is 30 * 4/(4 + k) rounded half away
+    from zero: 30, 24, 20, 17.142.. -> 17, 15, 13.33.. -> 13 (literals)."""
+    prog = O.build_program(G.family0(0), G.Params(replicas=1, eta_decay=4))
+    prog.eta = Fraction(prog.s_g, 1 << 32)
+    assert prog.eta_decay == 4
+    acc = [0]
+    steps = []
+    for k in range(6):
+        new, _ = O.lambda_step(prog, acc, [30], 1, k=k)
+        steps.append(new[0] - acc[0])
+        acc = new
+    assert steps == [30, 24, 20, 17, 15, 13]
+    # negative residual sums mirror them; a constant step ignores k
+    new, _ = O.lambda_step(prog, [0], [-30], 1, k=3)
+    assert new == [-17]
+    prog.eta_decay = 0
+    assert O.lambda_step(prog, [0], [30], 1, k=5)[0] == [30]
+
+
+def test_diminishing_step_sum_diverges_and_squares_converge():
+    """The step sizes meet the conditions of the surrogate subgradient method:
+    sum_k eta_k grows like H log K without bound, sum eta_k^2 stays below
+    eta^2 H (H + 1)."""
+    prog = O.build_program(G.family0(0), G.Params(replicas=1, eta=Fraction(1, 2), eta_decay=8))
+    s1 = s2 = Fraction(0)
+    for k in range(4000):
+        e = O.step_size(prog, k)
+        assert e == Fraction(1, 2) * Fraction(8, 8 + k)
+        s1 += e
+        s2 += e * e
+    assert s1 > Fraction(1, 2) * 8 * 6  # H (ln(4008/8) ~ 6.2) eta
+    assert s2 < Fraction(1, 4) * 8 * 9
+
+
+def test_diminishing_step_index_is_capped():
+    prog = O.build_program(G.family0(0), G.Params(replicas=64, eta_decay=16))
+    lam_den = prog.eta.denominator * 64 * prog.s_g
+    assert prog.eta_kcap == min(((1 << 62) - 1) // lam_den - 16, (1 << 31) - 1)
+    assert O.step_size(prog, prog.eta_kcap + 1000) == O.step_size(prog, prog.eta_kcap)
+    assert O.step_size(prog, -3) == prog.eta  # before any round: k = 0
+
+
 def test_saturation_mask_is_sticky():
     prog = O.build_program(G.family0(0), G.Params(replicas=1))
     cap = prog.lq_max << 24

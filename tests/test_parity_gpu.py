@@ -121,6 +121,21 @@ def test_mkp_wide_dot_path(need_gpu):
     run_parity(prob, par, 2, label="MKP wide")
 
 
+@pytest.mark.parametrize("kind", ["qkp", "mkp"])
+def test_diminishing_step(need_gpu, kind):
+    """Multiplier step eta H / (H + k): the whole loop against the oracle, with
+    the multipliers moving every round and the step shrinking."""
+    if kind == "qkp":
+        prob = G.qkp(60, Fraction(1, 2), G.rng_for(992, 0))
+        par = G.Params(replicas=64, sweeps=80, beta=Fraction(10), eta=Fraction(20), eta_decay=3)
+    else:
+        prob = G.mkp(80, 5, G.rng_for(992, 1))
+        par = G.Params(replicas=128, sweeps=60, beta=Fraction(50), eta=Fraction(2), alpha=Fraction(5),
+                       eta_decay=2)
+    ref, _ = run_parity(prob, par, 6, label=f"diminishing step {kind}")
+    assert len({tuple(e["lq"]) for e in ref["rounds"]}) >= 4
+
+
 def test_fixed_beta_and_zero_beta(need_gpu):
     prob = G.family0(1)
     run_parity(prob, G.Params(replicas=64, sweeps=20, beta=Fraction(3), fixed_beta=True), 2,
@@ -182,7 +197,7 @@ def _spot_check_rounds(prob, par, sample, rounds=1, lq0=None):
             assert (x[r] == xo[0]).all(), f"round {k} replica {r}: state differs"
             assert (out["g"][r] == go[0]).all(), f"round {k} replica {r}: residual differs"
         best = O.best_update(best, k, pr, fe, x[:, :prog.n])
-        acc, lq = O.lambda_step(prog, acc, [int(v) for v in out["G"]])
+        acc, lq = O.lambda_step(prog, acc, [int(v) for v in out["G"]], k=k)
         assert [int(v) for v in lam] == lq, f"round {k}: multiplier step differs"
         assert out["round"] == k + 1
     got = inst.best_feasible()
