@@ -262,15 +262,34 @@ typedef struct pbit_batch pbit_batch; /* opaque */
 /* Workspace bytes for a batch of count instances; 0 if any pair is invalid. */
 size_t pbit_batch_workspace_bytes(const pbit_problem *probs, const pbit_params *params, int32_t count);
 
+/* Launch layout of a batch (every layout gives the same results; the
+ * autotuner picks one per batch shape by timing):
+ *  blocks_quad    persistent workgroups of the quadratic family (0: as many
+ *                 as can be resident, one per CU times the occupancy);
+ *  blocks_linear  the same for the linear family;
+ *  split_percent  a linear member whose plain 256-replica chain is longer than
+ *                 split_percent/100 of the average linear load per CU runs as
+ *                 split tiles (one visiting and three producer waves per 64
+ *                 replicas, when its constants fit LDS); 0: none; -1: 200;
+ *  split_members  set by pbit_batch_layout_used: members run split (ignored
+ *                 on input). */
+typedef struct {
+    int32_t blocks_quad, blocks_linear, split_percent, split_members;
+} pbit_batch_layout;
+
 /* Creates a batch in dev_ws (caller-owned device memory, 256-byte aligned, at
  * least pbit_batch_workspace_bytes).  rounds[i] is member i's round budget
  * (NULL: unlimited); a member whose budget is spent is skipped by later rounds.
- * blocks caps the persistent grid of each kernel family (0: one workgroup per
- * resident slot).
- * Errors as pbit_create_instance; the message names the failing member. */
+ * layout NULL: {0, 0, -1}.
+ * Errors as pbit_create_instance (the message names the failing member), and
+ * PBIT_EINVAL for negative grid sizes or split_percent < -1. */
 pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *params, int32_t count,
-                              const int32_t *rounds, int32_t blocks, void *dev_ws, size_t ws_bytes,
-                              pbit_stream stream, pbit_batch **out);
+                              const int32_t *rounds, const pbit_batch_layout *layout, void *dev_ws,
+                              size_t ws_bytes, pbit_stream stream, pbit_batch **out);
+
+/* The layout a batch runs with (grids after the caps, the split rule in
+ * force and how many members it splits). */
+pbit_status pbit_batch_layout_used(const pbit_batch *batch, pbit_batch_layout *out);
 
 /* One round (annealing runs and epilogue) of every member with budget left.
  * Asynchronous on stream. */

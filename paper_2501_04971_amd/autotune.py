@@ -9,7 +9,9 @@ purely a speed question, answered by measurement:
   constants are staged in LDS or read from global memory, and the
   producer/consumer split (for the quadratic kernel with three or six
   producer waves);
-* batches: the persistent grid size.
+* batches: the rule that decides which linear members run as split tiles and
+  the linear family's persistent grid (timed on a probe of the whole batch
+  with every member's sweep count scaled down by one common factor).
 
 A probe run with a reduced sweep count times each candidate (the cost of a
 sweep does not depend on the sweep count) and the fastest is cached per shape
@@ -124,25 +126,58 @@ def apply(inst, prob, par, tune_missing: bool = True, path: str | None = None) -
     return entry
 
 
-def tune_batch(probs, pars, probe_sweeps: int = 40, reps: int = 2, path: str | None = None) -> dict:
-    """Times persistent grid sizes for a batch shape and caches the fastest
-    under a key of the member count and the largest member."""
-    probe = [dataclasses.replace(q, sweeps=min(q.sweeps, probe_sweeps)) for q in pars]
+def batch_key(probs, pars) -> str:
+    """Batches that share a key share a best layout: the member count and the
+    multiset of member shapes (kernel variant, padded spins, constraints,
+    256-replica tiles, sweeps)."""
+    import hashlib
+    shapes = sorted((int(i.variant), int(i.n_pad), int(i.m), (q.replicas + 255) // 256, int(q.sweeps))
+                    for i, q in ((B.pbit_plan(p, q), q) for p, q in zip(probs, pars)))
+    return f"batch-{len(probs)}-{hashlib.sha1(repr(shapes).encode()).hexdigest()[:12]}"
+
+
+def batch_candidates():
+    """Layouts tried for a batch: the split rule for linear members (200 % of
+    the average linear load per CU, the default, or 150 / 300 %, or no split)
+    and the linear family's grid (one workgroup per resident slot, or 224)."""
+    return [{"blocks_quad": 0, "blocks_linear": bl, "split_percent": sp}
+            for sp in (200, 150, 300, 0) for bl in (0, 224)]
+
+
+def probe_params(pars, probe_sweeps: int):
+    """Every member's sweep count divided by one common factor, so that the
+    members keep their relative costs (a sweep's cost does not depend on the
+    sweep count)."""
+    f = max(1, max(q.sweeps for q in pars) // probe_sweeps)
+    return [dataclasses.replace(q, sweeps=max(1, q.sweeps // f)) for q in pars]
+
+
+def tune_batch(probs, pars, probe_sweeps: int = 80, reps: int = 2, path: str | None = None) -> dict:
+    """Times every candidate layout on a probe of the batch (all members, sweep
+    counts scaled down together) and caches the fastest under batch_key."""
+    probe = probe_params(pars, probe_sweeps)
     timings = {}
-    n_cu = None
-    for blocks in (0, 128, 192, 384):
-        b = B.Batch(probs, probe, blocks=blocks)
-        items, nblk, _ = b.shape()
-        n_cu = n_cu or nblk
-        if str(nblk) in timings:
-            b.close()
-            continue
-        timings[str(nblk)] = _time_rounds(lambda: b.run(1, use_graph=True), reps)
+    for cand in batch_candidates():
+        b = B.Batch(probs, probe, layout=cand)
+        used = b.layout()
+        tag = f"{cand['split_percent']},{used['blocks_linear']}"
+        if tag not in timings:
+            timings[tag] = _time_rounds(lambda: b.run(1, use_graph=True), reps)
         b.close()
     best = min(timings, key=timings.get)
-    key = f"batch-{len(probs)}-r{_bucket_pow2(max(q.replicas for q in pars))}"
-    entry = {"blocks": int(best), "probe_ms": timings, "probe_sweeps": probe_sweeps}
+    sp, bl = (int(v) for v in best.split(","))
+    entry = {"layout": {"blocks_quad": 0, "blocks_linear": bl, "split_percent": sp}, "probe_ms": timings,
+             "probe_sweeps": [q.sweeps for q in probe[:1]] + [max(q.sweeps for q in probe)]}
     cache = load_cache(path)
-    cache[key] = entry
+    cache[batch_key(probs, pars)] = entry
     save_cache(cache, path)
     return entry
+
+
+def batch_layout(probs, pars, tune_missing: bool = True, path: str | None = None) -> dict | None:
+    """The cached layout for this batch shape (tuned first if missing and
+    tune_missing is set), as the layout argument of binding.Batch."""
+    entry = load_cache(path).get(batch_key(probs, pars))
+    if entry is None and tune_missing:
+        entry = tune_batch(probs, pars, path=path)
+    return None if entry is None else dict(entry["layout"])

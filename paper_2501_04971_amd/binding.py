@@ -45,6 +45,19 @@ class pbit_params(ctypes.Structure):
                 ("eta_decay_rounds", ctypes.c_int32)]
 
 
+class pbit_batch_layout(ctypes.Structure):
+    _fields_ = [("blocks_quad", ctypes.c_int32), ("blocks_linear", ctypes.c_int32),
+                ("split_percent", ctypes.c_int32), ("split_members", ctypes.c_int32)]
+
+
+def make_layout(layout=None, blocks: int = 0) -> pbit_batch_layout:
+    """layout: dict with any of blocks_quad, blocks_linear, split_percent
+    (missing keys: 0, 0, -1); blocks > 0 caps both families' grids."""
+    d = {"blocks_quad": blocks, "blocks_linear": blocks, "split_percent": -1}
+    d.update(layout or {})
+    return pbit_batch_layout(int(d["blocks_quad"]), int(d["blocks_linear"]), int(d["split_percent"]), 0)
+
+
 class pbit_plan_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("n_ext", ctypes.c_int32),
                 ("n_pad", ctypes.c_int32), ("words", ctypes.c_int32),
@@ -82,8 +95,9 @@ EXPORTS = {
     "pbit_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "pbit_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "pbit_create_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
-                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_batch_layout_used": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_batch_sample_round": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_batch_update_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -284,15 +298,23 @@ def pbit_batch_workspace_bytes(probs, pars) -> int:
     return int(lib().pbit_batch_workspace_bytes(ms.problems, ms.params, ms.count))
 
 
-def pbit_create_batch(probs, pars, rounds, workspace, blocks: int = 0, stream=None) -> int:
+def pbit_create_batch(probs, pars, rounds, workspace, blocks: int = 0, stream=None, layout=None) -> int:
     ms = _MarshalledSet(probs, pars)
     rv = None if rounds is None else np.ascontiguousarray(np.asarray(rounds, dtype=np.int32))
+    lay = make_layout(layout, blocks)
     handle = ctypes.c_void_p()
     _check(lib().pbit_create_batch(ms.problems, ms.params, ms.count,
-                                   None if rv is None else rv.ctypes.data, int(blocks),
+                                   None if rv is None else rv.ctypes.data, ctypes.byref(lay),
                                    workspace.data_ptr(), workspace.numel(),
                                    _stream_handle(stream), ctypes.byref(handle)))
     return int(handle.value)
+
+
+def pbit_batch_layout_used(batch: int) -> dict:
+    out = pbit_batch_layout()
+    _check(lib().pbit_batch_layout_used(batch, ctypes.byref(out)))
+    return {"blocks_quad": out.blocks_quad, "blocks_linear": out.blocks_linear,
+            "split_percent": out.split_percent, "split_members": out.split_members}
 
 
 def pbit_batch_sample_round(batch: int, stream=None) -> None:
@@ -482,7 +504,7 @@ class Batch:
     torch-owned workspace.  members[i] is an Instance view of member i (its
     lambda / residual vectors include any padding constraints)."""
 
-    def __init__(self, probs, pars, rounds=None, blocks: int = 0, stream=None):
+    def __init__(self, probs, pars, rounds=None, blocks: int = 0, stream=None, layout=None):
         import torch
         self.problems, self.params, self.stream = list(probs), list(pars), stream
         nbytes = pbit_batch_workspace_bytes(self.problems, self.params)
@@ -490,7 +512,7 @@ class Batch:
             # re-run through create for the error message
             nbytes = 256
         self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
-        self.handle = pbit_create_batch(self.problems, self.params, rounds, self.workspace, blocks, stream)
+        self.handle = pbit_create_batch(self.problems, self.params, rounds, self.workspace, blocks, stream, layout)
         self.members = [Instance(p, q, stream, _member=pbit_batch_member(self.handle, i))
                         for i, (p, q) in enumerate(zip(self.problems, self.params))]
 
@@ -517,6 +539,10 @@ class Batch:
     def shape(self):
         """(work items, persistent workgroups, LDS bytes per workgroup)."""
         return pbit_batch_shape(self.handle)
+
+    def layout(self) -> dict:
+        """The launch layout in force (grids per family, split rule, split members)."""
+        return pbit_batch_layout_used(self.handle)
 
     def close(self):
         if self.handle:

@@ -140,7 +140,7 @@ bool make_theta(std::vector<int32_t> &t)
 }
 
 struct Layout {
-    size_t theta, btab, J, acol, kbase, sa2, b, hprof, slack_off, slack_q;  // constants
+    size_t theta, btab, zsweep, J, acol, kbase, sa2, b, hprof, slack_off, slack_q;  // constants
     size_t kconst /* per-site records */, lam_acc, lam_q, round_k, G, best, best_x, feas;          // state
     size_t rx, rg, rprofit, rfeas;                                         // outputs
     size_t upload_end, total;
@@ -160,6 +160,7 @@ struct Plan {
     uint64_t seed = 0;
     uint32_t inst = 0;
     std::vector<int32_t> theta, btab, acol, hprof, slack_off, slack_q;
+    std::vector<ZtSweep> zsweep;   // [T] field-threshold constants of the split kernels
     std::vector<int64_t> kbase, sa2, b;
     std::vector<int8_t> J;  // n_pad x (n_pad + 16)
     Layout L{};
@@ -387,6 +388,33 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     P.sg2 = (int32_t)std::min<i128>(sg2 << zsh, INT32_MAX);
     P.ish = P.S + zsh - 32;
     P.irnd = (int64_t)1 << (P.S + zsh - 33);
+    // split kernels: threshold on the carried field, Zt = ceil(n 2^E / B_t),
+    // E = ish + 31, from A = floor(2^E / B_t) and rho = 2^E mod B_t (field_threshold)
+    P.zsweep.assign(P.T, ZtSweep{});
+    {
+        const int E = P.ish + 31;
+        if (E > 126) return fail(PBIT_ERANGE, "beta grid shift out of range");
+        for (int t = 0; t < P.T; ++t) {
+            ZtSweep &z = P.zsweep[t];
+            const int32_t B = P.btab[t];
+            if (B <= 0) {
+                z.sat = 1;
+                continue;
+            }
+            const u128 A = ((u128)1 << E) / (u128)B;
+            if (A >= ((u128)1 << 62)) {
+                z.sat = 1;
+                continue;
+            }
+            const u128 rho = ((u128)1 << E) % (u128)B;
+            z.fast = A < ((u128)1 << 48) ? 1 : 0;
+            z.a_hi = (int32_t)(A >> 31);
+            z.a_lo = (int32_t)(A & 0x7FFFFFFFu);
+            z.rho = (int32_t)rho;
+            z.bt = B;
+            z.rb = (double)(int32_t)rho / (double)B;
+        }
+    }
     if (P.ish <= 31) {
         P.hclo = -(int32_t)(1u << (P.ish - 1));
         P.hchi = (int32_t)((1u << (P.ish - 1)) - 1u);
@@ -459,6 +487,7 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     };
     L.theta = put(kThetaLen * 4);
     L.btab = put((size_t)P.T * 4);
+    L.zsweep = put((size_t)P.T * sizeof(ZtSweep));
     L.J = put(P.J.size());
     L.acol = put(P.acol.size() * 4);
     L.kbase = put((size_t)n_ext * 8);
@@ -570,6 +599,7 @@ struct pbit_batch {
     int blocks_lin = 0;
     size_t lds_lin = 0;
     int32_t *d_rounds = nullptr;
+    int split_percent = 200, n_split = 0;
     int blocks = 0;
     size_t lds = 0;
     hipGraph_t graph = nullptr;
@@ -639,6 +669,7 @@ pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *
     };
     cp(L.theta, P.theta.data(), P.theta.size() * 4);
     cp(L.btab, P.btab.data(), P.btab.size() * 4);
+    cp(L.zsweep, P.zsweep.data(), P.zsweep.size() * sizeof(ZtSweep));
     cp(L.J, P.J.data(), P.J.size());
     cp(L.acol, P.acol.data(), P.acol.size() * 4);
     cp(L.kbase, P.kbase.data(), P.kbase.size() * 8);
@@ -656,6 +687,7 @@ pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *
     d.J = reinterpret_cast<const int8_t *>(base + L.J);
     d.theta = reinterpret_cast<const int32_t *>(base + L.theta);
     d.Btab = reinterpret_cast<const int32_t *>(base + L.btab);
+    d.zsweep = reinterpret_cast<const ZtSweep *>(base + L.zsweep);
     d.acol = reinterpret_cast<const int32_t *>(base + L.acol);
     d.kbase = reinterpret_cast<const int64_t *>(base + L.kbase);
     d.sa2 = reinterpret_cast<const int64_t *>(base + L.sa2);
@@ -1158,11 +1190,15 @@ size_t pbit_batch_workspace_bytes(const pbit_problem *probs, const pbit_params *
 }
 
 pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *params, int32_t count,
-                              const int32_t *rounds, int32_t blocks, void *dev_ws, size_t ws_bytes,
-                              pbit_stream stream, pbit_batch **out)
+                              const int32_t *rounds, const pbit_batch_layout *layout, void *dev_ws,
+                              size_t ws_bytes, pbit_stream stream, pbit_batch **out)
 {
     if (!out) return fail(PBIT_EINVAL, "null output handle");
-    if (blocks < 0) return fail(PBIT_EINVAL, "blocks must be >= 0");
+    pbit_batch_layout lay{0, 0, -1, 0};
+    if (layout) lay = *layout;
+    if (lay.blocks_quad < 0 || lay.blocks_linear < 0) return fail(PBIT_EINVAL, "grid sizes must be >= 0");
+    if (lay.split_percent < -1) return fail(PBIT_EINVAL, "split_percent must be >= -1");
+    if (lay.split_percent == -1) lay.split_percent = 200;
     BatchSizes z;
     pbit_status st = batch_sizes(probs, params, count, z);
     if (st != PBIT_OK) return st;
@@ -1221,8 +1257,13 @@ pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *para
     // both lengthened its rounds).
     std::vector<char> split(count, 0);
     const int64_t load = lin_total / cus;
-    for (int i = 0; i < count; ++i)
-        split[i] = lin_cost[i] > 2 * load && linear_split_bytes(b->members[i]->plan) <= kMaxLds;
+    int n_split = 0;
+    for (int i = 0; i < count; ++i) {
+        split[i] = lay.split_percent > 0 && lin_cost[i] >= 0 &&
+                   (i128)lin_cost[i] * 100 > (i128)lay.split_percent * load &&
+                   linear_split_bytes(b->members[i]->plan) <= kMaxLds;
+        n_split += split[i];
+    }
     for (int i = 0; i < count; ++i) {
         const Plan &P = b->members[i]->plan;
         const int code = batch_variant_code(P.variant, P.nb, P.m);
@@ -1248,8 +1289,11 @@ pbit_status pbit_create_batch(const pbit_problem *probs, const pbit_params *para
     if (e == hipSuccess && n_quad > 0) e = sweep_batch_prepare(false, b->lds, &per_cu);
     if (e == hipSuccess && n_lin > 0) e = sweep_batch_prepare(true, b->lds_lin, &per_cu_lin);
     if (e == hipSuccess && (per_cu < 1 || per_cu_lin < 1)) e = hipErrorInvalidConfiguration;
-    b->blocks = n_quad == 0 ? 0 : (blocks > 0 ? std::min(blocks, n_quad) : std::min(n_quad, cus * per_cu));
-    b->blocks_lin = n_lin == 0 ? 0 : (blocks > 0 ? std::min(blocks, n_lin) : std::min(n_lin, cus * per_cu_lin));
+    const int bq = lay.blocks_quad, bl = lay.blocks_linear;
+    b->blocks = n_quad == 0 ? 0 : (bq > 0 ? std::min(bq, n_quad) : std::min(n_quad, cus * per_cu));
+    b->blocks_lin = n_lin == 0 ? 0 : (bl > 0 ? std::min(bl, n_lin) : std::min(n_lin, cus * per_cu_lin));
+    b->split_percent = lay.split_percent;
+    b->n_split = n_split;
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_insts, b->dev.data(), b->dev.size() * sizeof(DevInstance), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -1348,6 +1392,16 @@ pbit_status pbit_batch_shape(const pbit_batch *b, int32_t *items, int32_t *block
     if (items) *items = (int32_t)b->items.size();
     if (blocks) *blocks = b->blocks + b->blocks_lin;
     if (lds_bytes) *lds_bytes = std::max(b->lds, b->lds_lin);
+    return PBIT_OK;
+}
+
+pbit_status pbit_batch_layout_used(const pbit_batch *b, pbit_batch_layout *out)
+{
+    if (!b || !out) return fail(PBIT_EINVAL, "null batch or output");
+    out->blocks_quad = b->blocks;
+    out->blocks_linear = b->blocks_lin;
+    out->split_percent = b->split_percent;
+    out->split_members = b->n_split;
     return PBIT_OK;
 }
 

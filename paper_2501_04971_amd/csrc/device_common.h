@@ -90,6 +90,47 @@ __host__ __device__ __forceinline__ int64_t field_hi(int64_t Z, int32_t B, int64
     return (int64_t)(int32_t)(Z >> 32) * (int64_t)B + (int64_t)(lo >> 32) + irnd;
 }
 
+// Threshold on the carried field itself.  With n = 2 j* - 1 (j* the table
+// position of the draw) the split kernels' decision
+//   [floor(Z B_t / 2^32) >= j* 2^ish - 2^(ish-1)] = [Z B_t >= n 2^E]
+// (E = ish + 31) is [Z >= Zt] with Zt = ceil(n 2^E / B_t) for B_t > 0; when
+// B_t = 0 it is [n < 0].  Since |Z| < 2^62, a threshold beyond +-2^62 acts as
+// +-2^62.  Zt = n A + ceil(n rho / B_t) with A = floor(2^E / B_t), rho = 2^E
+// mod B_t (|n rho / B_t| < 2^14); the last term is estimated in double and
+// fixed by one exact check (0 <= q B_t - n rho < B_t), the double's error
+// being below 2^-38.  The whole result is exact.
+__host__ __device__ __forceinline__ int64_t field_threshold(int32_t n, const ZtSweep &z)
+{
+    constexpr int64_t kSat = (int64_t)1 << 62;
+    if (z.sat) return n < 0 ? -kSat : kSat;
+    const int64_t nr = (int64_t)n * z.rho;
+    int32_t q = (int32_t)ceil((double)n * z.rb);
+    const int64_t e = (int64_t)q * z.bt - nr;
+    q += e < 0 ? 1 : (e >= (int64_t)z.bt ? -1 : 0);
+    // |n A| >= (2^31 + 2^16) 2^31 - 2^45 > 2^62 once |n a_hi| exceeds 2^31 + 2^16;
+    // below that n A + q stays under 2^63
+    const int64_t hp = (int64_t)n * z.a_hi;
+    constexpr int64_t lim = ((int64_t)1 << 31) + ((int64_t)1 << 16);
+    const int64_t hc = hp > lim ? lim : (hp < -lim ? -lim : hp);  // (clamped: no overflow below)
+    const int64_t zt = hc * ((int64_t)1 << 31) + (int64_t)n * z.a_lo + q;
+    if (hp > lim || zt > kSat) return kSat;
+    if (hp < -lim || zt < -kSat) return -kSat;
+    return zt;
+}
+
+// field_threshold for a sweep with fast = 1 (A < 2^48, no saturation): the
+// double estimate v of n rho / B_t is within 2^-37 of the exact value, so
+// ceil(v) is exact unless v lies within 2^-30 of an integer; such draws (and
+// only they) set *near and must be redone with field_threshold.
+__host__ __device__ __forceinline__ int64_t field_threshold_fast(int32_t n, const ZtSweep &z, bool *near)
+{
+    const double v = (double)n * z.rb;
+    const double c = ceil(v);
+    *near = fabs(v - rint(v)) < 0x1p-30;
+    const int32_t hp = n * z.a_hi;
+    return (int64_t)hp * ((int64_t)1 << 31) + (int64_t)n * z.a_lo + (int64_t)(int32_t)c;
+}
+
 // Threshold on field_hi equivalent to a threshold index: for -2304 < js <= 2304,
 // [clamp(floor(hi / 2^ish), +-2304) >= js] = [hi >= js 2^ish], and since
 // |hi| < 2^62 a product that would not fit is saturated to +-2^62.

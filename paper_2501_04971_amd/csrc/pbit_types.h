@@ -17,12 +17,26 @@ constexpr int kBatchSplit = 0x100;   // work-item code flag: split (1 + 3 waves,
 // producer/consumer kernels: double-buffered threshold ring (32 sites x 64 lanes)
 constexpr size_t kRingBytes = 2 * 32 * 64 * 8;
 
+// Per-sweep constants of the threshold on the field itself used by the split
+// kernels (see field_threshold): for B_t > 0, A = floor(2^E / B_t) =
+// a_hi 2^31 + a_lo, rho = 2^E mod B_t and rb = rho / B_t as a double, with
+// E = S' - 1 (S' = S + u the shift of the carried field); sat = 1 when the
+// threshold is +-2^62 by the sign alone (B_t = 0, or A >= 2^62); fast = 1 when
+// A < 2^48 (then |n A| < 2^62 for every |n| < 2^14: field_threshold_fast).
+struct ZtSweep {
+    int32_t a_lo, a_hi, rho, bt;
+    double rb;
+    int32_t sat;
+    int32_t fast;   // 1: A < 2^48, so n a_hi fits 31 bits and nothing saturates
+};
+
 // Everything a kernel needs about one instance; passed by value.
 struct DevInstance {
     // constants written once at create
     const int8_t *J;          // quadratic: slabs of 32 rows x (n_pad + 16) bytes, slab stride 1 KB x (nb + 1)
     const int32_t *theta;     // [kThetaLen]
     const int32_t *Btab;      // [T] beta grid
+    const ZtSweep *zsweep;    // [T] constants of the field thresholds (split kernels)
     const int32_t *acol;      // [n_ext][m] extended constraint coefficients, site-major
     const int64_t *kbase;     // [n_ext] 256 s_g^2 h_i - Sa_i
     const int64_t *sa2;       // [n_ext] 2 Sa_i,  Sa_i = s_f Pq |a_i|^2

@@ -73,13 +73,10 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
         soff[k] = d.slack_off[k];
         sq[k] = d.slack_q[k];
     }
-    int32_t Bnext = d.Btab[0];
     int buf = 0;
     for (int c = 0; c < total; ++c) {
         const int w = c - (c / words) * words;
         if (wave == 0) {
-            const int32_t Bt = Bnext;
-            Bnext = d.Btab[(c + 1 < total ? c + 1 : c) / words];
             const int64_t *rg = ring + buf * 32 * 64;
             const int base = w * 32;
             if (w < owords) {
@@ -91,14 +88,14 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
 #pragma unroll
                 for (int s = 0; s < 32; ++s) {
                     const int i = base + s;
-                    const int64_t hthr = rg[s * 64 + lane];
+                    const int64_t zt = rg[s * 64 + lane];
                     const uint32_t xo = (xw0 >> s) & 1u;
                     const int32_t *a = ac + i * M;
                     const int64_t K = kr[2 * i + xo];
                     const int64_t dd = residual_dot<M, WIDE>(a, g);
                     const int64_t Z = WIDE ? K + dd * (int64_t)negk2 : K + (int64_t)(int32_t)dd * negk2;
                     // sites past the original items belong to the slack loop: never flip here
-                    const uint32_t xn = (uint32_t)(field_hi(Z, Bt, 0) >= hthr) & (uint32_t)(s < rem);
+                    const uint32_t xn = (uint32_t)(Z >= zt) & (uint32_t)(s < rem);
                     const int32_t delta = (int32_t)xn - (int32_t)xo;
 #pragma unroll
                     for (int k = 0; k < M; ++k) g[k] = WIDE ? g[k] + delta * a[k] : mad_i24(delta, a[k], g[k]);
@@ -116,11 +113,11 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
                     const uint32_t sk0 = sk[k];
                     for (int q = q0; q < q1; ++q) {
                         const int i = off + q;
-                        const int64_t hthr = rg[(i - base) * 64 + lane];
+                        const int64_t zt = rg[(i - base) * 64 + lane];
                         const uint32_t xo = (sk0 >> q) & 1u;
                         const int64_t K = kr[2 * i + xo];
                         const int64_t Z = K + (((int64_t)g[k] * negk2) << q);
-                        const uint32_t xn = field_hi(Z, Bt, 0) >= hthr ? 1u : 0u;
+                        const uint32_t xn = Z >= zt ? 1u : 0u;
                         g[k] += ((int32_t)xn - (int32_t)xo) << q;
                         sk[k] = (sk[k] & ~(1u << q)) | (xn << q);
                     }

@@ -7,16 +7,17 @@
 //  * the Philox4x32-10 draw u24 of the visit (same counters as everywhere);
 //  * its threshold index j* = min{ j : Theta[j] > u24 } (Theta is
 //    non-decreasing, so x_i = [u24 < Theta[idx]] = [idx >= j*]), from the
-//    inverse of tanh checked against the table, with an exact bisection for
-//    the rare draws in its flat tails;
+//    inverse of tanh checked against one adjacent pair of table entries (a
+//    third entry for guesses one position off, an exact bisection for the
+//    rare draws in the table's flat tails);
 //  * the threshold on the field itself: with
 //      hi = floor((Z B_t + 2^(S'-1)) / 2^32),  idx = clamp(floor(hi / 2^ish)),
-//    and -2304 < j* <= 2304, [idx >= j*] = [hi >= j* 2^ish];  |hi| < 2^62, so
-//    j* 2^ish is saturated to +-2^62 where it would not fit;
+//    and -2304 < j* <= 2304, [idx >= j*] = [hi >= j* 2^ish] = [Z >= Zt] with
+//    Zt = ceil((2 j* - 1) 2^(ish+31) / B_t) (field_threshold: exact, from
+//    per-sweep constants);
 //  * the refill of the J slab two blocks ahead.
 //
-// The consumer's visit is then field, one 32x32->64 product and a 64-bit
-// compare; the per-site thresholds arrive through a double-buffered LDS ring
+// The consumer's visit is then the field and one 64-bit compare; the per-site thresholds arrive through a double-buffered LDS ring
 // (32 sites x 64 lanes x 8 bytes per block) and one workgroup barrier per
 // block hands buffers over.  The consumer also issues the next block's field
 // refresh on the matrix cores while it visits the current block (see
@@ -32,7 +33,7 @@ constexpr size_t quad_pc_lds_bytes()
     return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 3 * (size_t)1024 * (NB + 1) + kRingBytes;
 }
 
-// Consumer visit of site s: thresholds come from the ring.
+// Consumer visit of site s: thresholds on the field itself come from the ring.
 template <int s, int LS>
 __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8],
                                               const int64_t *ring)
@@ -41,16 +42,16 @@ __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], 
     // block-start copy: the record load below then waits on no earlier decision
     const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
     const int64_t *cur = v.rec + 4 * s;
-    const int64_t hthr = ring[s * 64 + (threadIdx.x & 63)];
+    const int64_t thr = ring[s * 64 + (threadIdx.x & 63)];
     int32_t f = v.F[s];
     const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + s * LS);
 #pragma unroll
     for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
     const int64_t meta = cur[3];
-    // v.k2 holds -k2 here; the ring holds the threshold less the rounding term
+    // v.k2 holds -k2 here; the ring holds the threshold on the field itself
     // (the record holds K0, K1 in its first two words: indexed by the old state)
     const int64_t Z = cur[xo] + (int64_t)(f * 256) * v.sg2 + (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
-    const uint32_t xn = field_hi(Z, v.Bt, 0) >= hthr ? 1u : 0u;
+    const uint32_t xn = Z >= thr ? 1u : 0u;
     const int32_t delta = (int32_t)xn - (int32_t)xo;
     xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
     v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
@@ -119,18 +120,17 @@ __device__ __forceinline__ int theta_floor_guess(uint32_t u)
 
 // Producer p (0 .. NP-1 of NP = 3 or 6) fills its share of the ring buffer of
 // block blk (sites 32 blk .. 32 blk + 31) of sweep t: Philox groups g = p + NP k
-// (four sites each), k < KG = ceil(8 / NP).  A producer with fewer groups
-// computes the spare ones and discards them, so that all run the same code with
-// no branch between the table searches and the scheduler can overlap them.  The
+// (four sites each), k < KG.  The KG groups run side by side with no branch
+// between the table searches, so the scheduler can overlap them.  The
 // table position of each draw comes from theta_floor_guess, accepted only where
-// the table confirms it; the rest (flat tails, where many positions share a
-// value: a few draws in 10^6) is settled by an exact bisection over the whole
-// table.  Sites at or beyond N_ext never flip.
-template <int NP>
-__device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, int t, int blk, int64_t *ring,
-                                                   const int32_t *th, uint32_t kround, uint64_t m2)
+// the table confirms it: one pair read settles all but about one draw in 10^4,
+// a third entry those one position off, and an exact bisection over the whole
+// table the rest (flat tails, where many positions share a value: a few draws
+// in 10^6).  Sites at or beyond N_ext never flip.
+template <int NP, int KG>
+__device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int t, int blk, int64_t *ring,
+                                               const int32_t *th, uint32_t kround, uint64_t m2)
 {
-    constexpr int KG = (8 + NP - 1) / NP;
     constexpr int E = 4 * KG;
     const int lane = threadIdx.x & 63;
     const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
@@ -147,19 +147,36 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
         }
     }
     int lo[E], hi[E];
+    int dir[E];
+    bool miss = false;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        // fast path: check the guess and its neighbours against the table itself
-        // (th is non-decreasing: within th[g - 1] <= u < th[g + 2] the position
-        // is g - 1 plus the number of th[g], th[g + 1] that are <= u; bitwise
-        // operators, so that all four entries are read unconditionally)
+        // fast path: one read of the adjacent pair th[g], th[g + 1] settles the
+        // draw when th[g] <= u < th[g + 1] (position g); otherwise dir says on
+        // which side the position lies (th is non-decreasing)
         const int g = gs[e];
-        const uint32_t t0 = (uint32_t)th[g - 1], t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1],
-                       t3 = (uint32_t)th[g + 2];
-        const int found = g - 1 + (int)(t1 <= u[e]) + (int)(t2 <= u[e]);
-        const bool ok = ((t0 <= u[e]) & (u[e] < t3)) | (p + NP * (e >> 2) >= 8);  // (a discarded group needs no search)
-        lo[e] = ok ? found : 0;
-        hi[e] = ok ? found : kThetaLen - 1;
+        const uint32_t t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1];
+        const bool skip = p + NP * (e >> 2) >= 8;  // a discarded group needs no search
+        dir[e] = skip ? 0 : (t1 > u[e] ? -1 : (t2 <= u[e] ? 1 : 0));
+        lo[e] = g;
+        hi[e] = g;
+        miss = miss || dir[e] != 0;
+    }
+    // second chance for the draws whose guess is one position off (about one
+    // draw in 10^4, so a wave takes this branch for a minority of blocks): the
+    // entry beyond the pair confirms position g - 1 or g + 1; anything further
+    // off (the flat tails of the table) goes to the bisection below
+    if (__ballot(miss)) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (dir[e] != 0) {
+                const int g = gs[e];
+                const uint32_t t3 = (uint32_t)th[dir[e] < 0 ? g - 1 : g + 2];
+                const bool ok = dir[e] < 0 ? t3 <= u[e] : u[e] < t3;
+                lo[e] = ok ? g + dir[e] : 0;
+                hi[e] = ok ? g + dir[e] : kThetaLen - 1;
+            }
+        }
     }
     // exact bisection for the draws the fast path did not settle: th[lo] <= u
     // holds throughout (th[0] = 0), and the search ends at the largest such lo
@@ -178,21 +195,54 @@ __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, 
             }
         }
     }
-    // thresholds j* 2^ish - irnd; |j*| < 2^12, so without saturation whenever
-    // ish <= 50 (the common case, uniform per instance)
-    const bool nosat = d.ish <= 50;
+    // Thresholds on the carried field, Zt = ceil((2 j* - 1) 2^E / B_t), exact,
+    // from the sweep's constants (a uniform load).  Nearly every sweep takes
+    // the short form; a draw whose estimate lies next to an integer (about one
+    // in 10^9) makes its wave redo that draw exactly.  The thresholds are
+    // stored after all of them are known (stores between the computations
+    // made the whole kernel a third slower, measured).
+    const ZtSweep zs = d.zsweep[t];
+    int64_t h[E];
+    if (zs.fast) {
+        bool near[E], any = false;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            h[e] = field_threshold_fast(2 * (lo[e] + 1 - kThetaHalf) - 1, zs, &near[e]);
+            any = any || near[e];
+        }
+        if (__ballot(any)) {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (near[e]) h[e] = field_threshold(2 * (lo[e] + 1 - kThetaHalf) - 1, zs);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) h[e] = field_threshold(2 * (lo[e] + 1 - kThetaHalf) - 1, zs);
+    }
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
         if (p + NP * k < 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int s = 4 * (p + NP * k) + q;
-                const int js = lo[4 * k + q] + 1 - kThetaHalf;
-                const int64_t h = (nosat ? (int64_t)js * ((int64_t)1 << d.ish) : index_threshold(js, d.ish)) - d.irnd;
-                ring[s * 64 + lane] = blk * 32 + s < d.n_ext ? h : INT64_MAX;
+                ring[s * 64 + lane] = blk * 32 + s < d.n_ext ? h[4 * k + q] : INT64_MAX;
             }
         }
     }
+}
+
+// Producer p owns the Philox groups p, p + NP, p + 2 NP, ... below 8: the first
+// 8 - NP (KMAX - 1) producers take KMAX of them, the others one fewer (with
+// NP = 6, two per SIMD, the SIMDs then carry 3, 3 and 2 groups).
+template <int NP>
+__device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, int t, int blk, int64_t *ring,
+                                                   const int32_t *th, uint32_t kround, uint64_t m2)
+{
+    constexpr int KMAX = (8 + NP - 1) / NP;
+    if (p + NP * (KMAX - 1) < 8)
+        produce_groups<NP, KMAX>(d, p, t, blk, ring, th, kround, m2);
+    else
+        produce_groups<NP, KMAX - 1>(d, p, t, blk, ring, th, kround, m2);
 }
 
 // Producer p's share of the next J slab (quadratic kernel): loaded into
@@ -303,11 +353,10 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     int buf = 0;         // ring buffer of block step c
     int b0 = 0, b1 = 1;  // slab buffers of steps c and c + 1 (c % 3, (c + 1) % 3)
     for (int c = 0; c < total; ++c) {
-        const int t = c / NB, blk = c - (c / NB) * NB;
+        const int blk = c - (c / NB) * NB;
         const int b2 = b1 == 2 ? 0 : b1 + 1;
         if (wave == 0) {
             const int8_t *slab = slabs + b0 * SLAB;
-            v.Bt = d.Btab[t];
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             v.rec = site + 4 * (blk * 32);

@@ -13,11 +13,14 @@ penalty method (Sec. IV-A, Table 2) on 20 synthetic QKP instances with N = 100
   saim      Algorithm 1 itself, one chain per instance: 2000 annealing runs of
             1000 MCS, lambda stepped after each (Table 1: P = 2dN, beta_max 10,
             eta 20);
-  penalty   the penalty method with the same budget and P (lambda = 0, eta = 0,
-            2000 independent runs);
+  p2dn      the penalty method at SAIM's P = 2dN (lambda = 0, eta = 0, 2000
+            independent runs of 1000 MCS): shows that P is sub-critical and
+            gives the critical-penalty estimate below;
   tuned     the penalty method with 10 runs of 2*10^5 MCS at a P raised from
             2dN over a coarse ladder until at least 20 % of the runs are
-            feasible (Sec. IV-A's tuning protocol).
+            feasible (Sec. IV-A's tuning protocol);
+  penalty   the penalty method in SAIM's run structure, 2000 runs of 1000 MCS,
+            at the tuned P (the paper's same-budget comparison).
 mkp100 runs Algorithm 1 on 10 synthetic MKP instances with N = 100, M = 5
 (Table 1: P = 5dN, beta_max 50, eta 0.05, 5000 runs of 1000 MCS) and the
 remedies the paper names for the low MKP feasibility (Sec. IV-B) plus the
@@ -54,7 +57,7 @@ from . import generators as G
 
 QKP_SAIM = dict(sweeps=1000, beta=Fraction(10), eta=Fraction(20), alpha=Fraction(2))
 MKP_SAIM = dict(sweeps=1000, beta=Fraction(50), eta=Fraction(1, 20), alpha=Fraction(5))
-TUNE_LADDER = [2, 5, 10, 20, 40, 70, 100, 150, 200, 300, 500, 1000, 2000]  # P / (d N)
+TUNE_LADDER = [2, 5, 10, 20, 40, 70, 100, 150, 200, 300, 500, 700, 1000]  # P / (d N)
 
 
 def qkp100_instances():
@@ -127,33 +130,65 @@ def cmd_qkp100(args):
     pars = [G.Params(replicas=1, instance_id=i, **QKP_SAIM) for i in range(len(probs))]
     res["arms"]["saim"] = dict(run_chains(probs, pars, args.rounds), replicas=1, rounds=args.rounds)
 
-    print("penalty: same budget and P, lambda = 0", flush=True)
+    print("p2dn: penalty method at P = 2dN, lambda = 0", flush=True)
     pars = [G.Params(replicas=args.rounds, sweeps=1000, beta=Fraction(10), eta=Fraction(0), alpha=Fraction(2),
                      instance_id=i) for i in range(len(probs))]
-    res["arms"]["penalty"] = {"samples": run_samples(probs, pars), "replicas": args.rounds}
+    res["arms"]["p2dn"] = {"samples": run_samples(probs, pars), "replicas": args.rounds}
 
     print("tuned: 10 runs of 2e5 MCS, P raised until >= 20 % feasible", flush=True)
     chosen = [None] * len(probs)
     samples = [None] * len(probs)
+    last = [None] * len(probs)      # (P / dN, samples) of the largest P tried
+    exhausted = [False] * len(probs)
     for c in TUNE_LADDER:
-        todo = [i for i in range(len(probs)) if chosen[i] is None]
-        if not todo:
-            break
-        pars = []
-        for i in todo:
+        todo, pars = [], []
+        for i in range(len(probs)):
+            if chosen[i] is not None or exhausted[i]:
+                continue
             # P = c d N_ext on the 2^-8 grid
             pq = round(Fraction(256 * c) * probs[i].density * res["n_ext"][i])
-            pars.append(G.Params(replicas=10, sweeps=args.tuned_sweeps, beta=Fraction(10), eta=Fraction(0),
-                                 p_q=int(pq), instance_id=1000 + i))
+            par = G.Params(replicas=10, sweeps=args.tuned_sweeps, beta=Fraction(10), eta=Fraction(0),
+                           p_q=int(pq), instance_id=1000 + i)
+            try:
+                B.pbit_plan(probs[i], par)
+            except B.PbitError:
+                exhausted[i] = True  # P beyond the exact integer range of the kernels
+                continue
+            todo.append(i)
+            pars.append(par)
+        if not todo:
+            break
         t0 = time.perf_counter()
         got = run_samples([probs[i] for i in todo], pars)
         for i, s in zip(todo, got):
+            last[i] = (c, s)
             if sum(s["feasible"]) >= 2:
                 chosen[i], samples[i] = c, s
         print(f"  P = {c} dN: {len(todo)} runs, {sum(ch == c for ch in chosen)} accepted, "
               f"{time.perf_counter() - t0:.1f} s", flush=True)
+    # instances that never reached 20 % report their largest P
+    for i in range(len(probs)):
+        if chosen[i] is None and last[i] is not None:
+            samples[i] = last[i][1]
     res["arms"]["tuned"] = {"p_over_dn": chosen, "samples": samples, "replicas": 10,
-                            "sweeps": args.tuned_sweeps}
+                            "sweeps": args.tuned_sweeps,
+                            "largest_tried": [None if l is None else l[0] for l in last]}
+
+    print("penalty: 2000 runs of 1000 MCS at the tuned P", flush=True)
+    todo, pars = [], []
+    for i in range(len(probs)):
+        c = chosen[i] if chosen[i] is not None else (last[i][0] if last[i] is not None else None)
+        if c is None:
+            continue
+        pq = round(Fraction(256 * c) * probs[i].density * res["n_ext"][i])
+        todo.append(i)
+        pars.append(G.Params(replicas=args.rounds, sweeps=1000, beta=Fraction(10), eta=Fraction(0), p_q=int(pq),
+                             instance_id=2000 + i))
+    got = run_samples([probs[i] for i in todo], pars)
+    pen = [None] * len(probs)
+    for i, s_ in zip(todo, got):
+        pen[i] = s_
+    res["arms"]["penalty"] = {"samples": pen, "replicas": args.rounds}
     with open(args.out, "w") as f:
         json.dump(res, f)
     print(json.dumps({"out": args.out}), flush=True)
@@ -260,16 +295,18 @@ def cmd_report(args):
         if exp == "qkp100":
             rows = []
             print("| instance | OPT | SAIM best | avg (feas %) | penalty best | avg (feas %) | tuned best | avg (feas %) "
-                  "| tuned P/dN | P_hat_C / dN | 2dN / P_hat_C |")
-            print("|---|---|---|---|---|---|---|---|---|---|---|")
+                  "| tuned P/dN | P=2dN feas % | P_hat_C / dN | 2dN / P_hat_C |")
+            print("|---|---|---|---|---|---|---|---|---|---|---|---|")
             for j, name in enumerate(res["instances"]):
                 opt = opts[j].profit
                 a = _chain_stats(res["arms"]["saim"], j, opt)
-                b = _sample_stats(res["arms"]["penalty"]["samples"][j], opt)
+                ps = res["arms"]["penalty"]["samples"][j]
+                b = _sample_stats(ps, opt) if ps else {"best": None, "avg": None, "feasible": 0.0, "optimal": False}
                 ts = res["arms"]["tuned"]["samples"][j]
                 c = _sample_stats(ts, opt) if ts else {"best": None, "avg": None, "feasible": 0.0, "optimal": False}
                 # critical-penalty estimate from the penalty arm's samples
-                s = res["arms"]["penalty"]["samples"][j]
+                s = res["arms"]["p2dn"]["samples"][j]
+                feas2 = 100.0 * np.mean(s["feasible"])
                 prof = np.asarray(s["profit"], dtype=np.int64)
                 g2 = np.asarray(s["g2"], dtype=np.int64)
                 sel = (g2 > 0) & (prof > opt)
@@ -278,9 +315,11 @@ def cmd_report(args):
                            default=None)
                 dn = base[j].density * res["n_ext"][j]
                 p_rule = Fraction(res["p_q_rule"][j], 256)
-                rows.append((a, b, c, res["arms"]["tuned"]["p_over_dn"][j], phat, dn, p_rule))
-                print(f"| {name} | {opt} | {_fmt(a).replace(' | ', ' | ', 1)} | {_fmt(b)} | {_fmt(c)} | "
-                      f"{res['arms']['tuned']['p_over_dn'][j]} | "
+                rows.append((a, b, c, res["arms"]["tuned"]["p_over_dn"][j], phat, dn, p_rule, feas2))
+                tp = res["arms"]["tuned"]["p_over_dn"][j]
+                if tp is None:
+                    tp = f"({res['arms']['tuned']['largest_tried'][j]}, < 20 %)"
+                print(f"| {name} | {opt} | {_fmt(a)} | {_fmt(b)} | {_fmt(c)} | {tp} | {feas2:.0f} | "
                       f"{'—' if phat is None else f'{float(phat / dn):.1f}'} | "
                       f"{'—' if phat is None else f'{float(p_rule / phat):.3f}'} |")
             for key, label in (("best", "best"), ("avg", "avg"), ("feasible", "feasible %")):

@@ -44,3 +44,46 @@ def test_tuned_layout_is_used_and_exact(need_gpu, tmp_path):
     ref = O.saim(prob, par, 1, nthreads=8)["rounds"][0]
     assert (B.unpack_bits(out["x_bits"], ref["x"].shape[1]) == ref["x"]).all()
     assert (out["g"] == ref["g"]).all()
+
+
+def test_batch_key_and_candidates():
+    members = [G.workload(3, i) for i in range(4)]
+    probs, pars = [p for p, _, _ in members], [q for _, q, _ in members]
+    k = A.batch_key(probs, pars)
+    assert k.startswith("batch-4-") and k == A.batch_key(probs[::-1], pars[::-1])  # order-free
+    assert k != A.batch_key(probs[:3], pars[:3])
+    cands = A.batch_candidates()
+    assert {c["split_percent"] for c in cands} == {0, 150, 200, 300}
+    probe = A.probe_params(pars, 80)
+    # one common factor: the members keep their sweep ratio
+    assert [q.sweeps for q in probe] == [q.sweeps // (max(p.sweeps for p in pars) // 80) for q in pars]
+
+
+@pytest.mark.gpu
+def test_tuned_batch_layout_is_used_and_exact(need_gpu, tmp_path):
+    """A tuned mixed batch is re-created with the timed layout and its round is
+    the oracle's, member by member."""
+    from oracle import oracle as O
+    path = str(tmp_path / "tiling.json")
+    small = []
+    for i in range(6):
+        p, q, _ = G.workload(3, i)
+        small.append((p, G.Params(replicas=64, sweeps=q.sweeps // 50, beta=q.beta, eta=q.eta, alpha=q.alpha,
+                                  instance_id=q.instance_id)))
+    probs, pars = [p for p, _ in small], [q for _, q in small]
+    entry = A.tune_batch(probs, pars, probe_sweeps=10, reps=1, path=path)
+    assert len(entry["probe_ms"]) >= 4
+    lay = A.batch_layout(probs, pars, tune_missing=False, path=path)
+    assert lay == entry["layout"]
+    b = B.Batch(probs, pars, rounds=[1] * len(small), layout=lay)
+    used = b.layout()
+    assert used["split_percent"] == lay["split_percent"]
+    assert lay["blocks_linear"] == 0 or used["blocks_linear"] <= lay["blocks_linear"]
+    b.run(1, use_graph=True)
+    for i, (p, q) in enumerate(small):
+        out = b.members[i].round_outputs()
+        ref = O.saim(p, q, 1, nthreads=8)["rounds"][0]
+        x = B.unpack_bits(out["x_bits"], ref["x"].shape[1])
+        assert (x == ref["x"]).all(), f"member {i}"
+        assert (out["g"][:, :p.m] == ref["g"]).all()
+    b.close()
