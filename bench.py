@@ -182,6 +182,40 @@ def learned_start_summary(count: int = 64, rounds: int = 150):
     return res
 
 
+def concurrent_instances(workload: int, count: int, rounds: int):
+    """count instances of the workload (indices 0 .. count-1), each on a stream
+    of its own, all rounds queued before any is waited on: the chip-level rate
+    for the workload's own shape (one instance of the QKP N=300 workload holds
+    64 of the 256 CUs).  Streams keep the default priority."""
+    import torch
+    from paper_2501_04971_amd import binding as B
+    from paper_2501_04971_amd import generators as G
+    streams = [torch.cuda.Stream() for _ in range(count)]
+    insts, updates = [], 0
+    for i, st in enumerate(streams):
+        prob, par, _ = G.workload(workload, i)
+        with torch.cuda.stream(st):
+            inst = B.Instance(prob, par, stream=st)
+        insts.append(inst)
+        updates += par.replicas * inst.info.n_ext * par.sweeps
+    for inst in insts:  # warm-up round
+        inst.sample_round()
+        inst.update_lambda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        for inst in insts:
+            inst.sample_round()
+            inst.update_lambda()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for inst in insts:
+        inst.close()
+    return {"instances": count, "rounds": rounds, "ms_per_round": dt / rounds * 1e3,
+            "spin_updates_per_s": updates * rounds / dt,
+            "timing": "host wall clock around all streams (synchronised before and after)"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +225,8 @@ def main() -> int:
     ap.add_argument("--instance", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the samples-to-target comparison")
+    ap.add_argument("--concurrent", type=int, default=4,
+                    help="also time this many instances of the workload side by side (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -328,6 +364,8 @@ def main() -> int:
         "wall_s": wall,
         "best_feasible_profit": None if best is None else best[0],
     }
+    if args.concurrent > 1 and not batch:
+        out["concurrent"] = concurrent_instances(args.workload, args.concurrent, max(2, min(args.steps, 5)))
     if not args.no_learned and args.workload == 2:
         out["samples_to_target"] = learned_start_summary()
     if not args.no_cpu_baseline:
