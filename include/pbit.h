@@ -89,7 +89,22 @@ typedef struct {
  *               surrogate subgradient ascent of Sec. III-A converges); 0 keeps
  *               eta constant as in Algorithm 1.  At most 2^20; k is capped where
  *               the step's 64-bit denominator would overflow (beyond 10^9
- *               rounds for every instance the bounds admit). */
+ *               rounds for every instance the bounds admit).
+ *  pt_slots     L > 0: parallel tempering as the Ising machine (Sec. III-B: the
+ *               machine inside Algorithm 1 is interchangeable) instead of
+ *               annealing: replicas form chains of L (replica c L + j starts at
+ *               ladder position j), held at the fixed ladder
+ *               beta_j = beta_max (j + 1) / L on the beta grid; after sweep t the
+ *               replicas at positions tau, tau + 1 (tau = t mod 2, 4, ...) swap
+ *               positions when j = floor(256 (beta_tau - beta_tau+1)(L_a - L_b))
+ *               >= 0 or u24 < round(2^24 exp(j / 256)) (Metropolis on the grid;
+ *               u24 from Philox(t, k | 2^31, c L + tau, instance_id)).  Each
+ *               chain's sample is its replica at position L - 1: the residual
+ *               sums, the best record and the multiplier step use those R / L
+ *               samples.  Quadratic instances only; L divides 64 and R;
+ *               beta_max > 0 and no fixed-beta mode (PBIT_EINVAL otherwise).
+ *               The multiplier range may be narrowed so that every energy
+ *               difference stays exact in 64 bits (PBIT_ERANGE if below 1). */
 typedef struct {
     int32_t replicas, sweeps;
     int32_t beta_num, beta_den;
@@ -100,6 +115,7 @@ typedef struct {
     uint32_t instance_id;
     int32_t fixed_beta;
     int32_t eta_decay_rounds;
+    int32_t pt_slots;
 } pbit_params;
 
 /* Host-side description of a compiled instance (no device needed). */
@@ -114,7 +130,7 @@ typedef struct {
     int32_t reserved;
     size_t workspace_bytes;
     /* layout of the buffer filled by pbit_round_outputs (byte offsets) */
-    size_t out_x, out_g, out_profit, out_feasible, out_G, out_lambda, out_round, out_sat, out_bytes;
+    size_t out_x, out_g, out_profit, out_feasible, out_G, out_lambda, out_round, out_sat, out_slot, out_bytes;
 } pbit_plan_info;
 
 /* Compiles the instance on the host and describes it.  Defines the encoding of
@@ -216,7 +232,10 @@ pbit_status pbit_best_feasible(pbit_instance *inst, int64_t *profit, uint8_t *x,
  *   out_round    int32  [1]         rounds completed
  *   out_sat      uint32 [1]         bit k set once lambda_k has been held at
  *                                   +-lq_max by a step or a set (sticky): from
- *                                   then on it no longer follows Algorithm 1 */
+ *                                   then on it no longer follows Algorithm 1
+ *   out_slot     int32  [R]         parallel tempering: final ladder position of
+ *                                   each replica (L - 1: the chain's sample);
+ *                                   zero without it */
 pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes, pbit_stream stream);
 
 /* Releases host-side state; the workspace may be reused afterwards.  Does not
@@ -409,6 +428,12 @@ const char *pbit_last_error(void);
 /* Threshold table the sampler uses: theta[j + 2304] = round(2^24 (1 + tanh(j/256))/2),
  * j = -2304..2304, written to host memory (4609 entries).  Host only. */
 pbit_status pbit_theta_table(int32_t *theta);
+
+/* Replica-exchange table of the parallel-tempering machine (pt_slots):
+ * x[i] = round(2^24 exp((i - 4608)/256)), i = 0..4608, the Metropolis
+ * acceptance exp(j/256) on the 2^-8 grid; written to host memory (4609
+ * entries).  Host only. */
+pbit_status pbit_exchange_table(int32_t *x);
 
 #ifdef __cplusplus
 }

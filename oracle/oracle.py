@@ -88,6 +88,23 @@ def theta_table() -> tuple:
     return tuple(out)
 
 
+XLEN = 4609                # exchange table: exp(j/256) for j = -4608 .. 0
+
+
+@lru_cache(maxsize=1)
+def exchange_table() -> tuple:
+    """X[i] = round(2^24 exp((i - 4608)/256)), i = 0..4608: the Metropolis
+    acceptance exp(Delta) of a replica exchange on the 2^-8 grid of Delta,
+    evaluated with 60 significant decimal digits."""
+    out = []
+    with localcontext() as ctx:
+        ctx.prec = 60
+        for i in range(XLEN):
+            v = Decimal(ONE24) * (Decimal(i - (XLEN - 1)) / Decimal(256)).exp()
+            out.append(int(v.to_integral_value(rounding=ROUND_HALF_EVEN)))
+    return tuple(out)
+
+
 # ---------------------------------------------------------------------------
 # the encoded instance
 
@@ -117,6 +134,14 @@ class Program:
     inst: int
     eta_decay: int = 0     # H of the diminishing step eta H / (H + k); 0: constant
     eta_kcap: int = 0      # largest k entering H + k
+    pt_slots: int = 0      # L > 0: parallel tempering chains of L replicas
+    Bl: list = None        # ladder grid values, L of them (hottest first)
+
+    @property
+    def samples(self) -> int:
+        """Samples per round that the multiplier step averages: every replica's
+        final state, or with parallel tempering each chain's coldest replica."""
+        return self.R // self.pt_slots if self.pt_slots else self.R
 
     def beta_values(self) -> list:
         """beta_t implied by the grid (for documentation and tests)."""
@@ -218,6 +243,34 @@ def build_program(prob: Problem, par: Params) -> Program:
     if lq_max < 256:
         raise OracleRangeError("multiplier range below 1.0")
 
+    # parallel tempering (the IM inside Algorithm 1 may be any sampler,
+    # Sec. III-B): chains of L replicas at the fixed ladder beta_max (j+1)/L on
+    # the grid above; the exchange compares energy differences D (L_a - L_b),
+    # which must stay below 2^61 in the carried scale 2^u (u = max(0, 34 - S)),
+    # so the multiplier range may be narrowed further
+    L = int(getattr(par, "pt_slots", 0))
+    Bl = None
+    if L:
+        if prob.kind != KIND_QKP:
+            raise ValueError("parallel tempering is built for the quadratic kernel")
+        if L < 2 or 64 % L != 0 or int(par.replicas) % L != 0:
+            raise ValueError("pt_slots must divide 64 and the replica count, and be >= 2")
+        if beta == 0 or par.fixed_beta:
+            raise ValueError("parallel tempering needs beta_max > 0 and no fixed-beta mode")
+        Bl = [round_half_up(Fraction(1 << S) * beta * (j + 1) / (L * den)) for j in range(L)]
+        u = max(0, 34 - S)
+        prof_max = int(np.abs(h).sum() + np.triu(np.abs(W), 1).sum())
+        gk = [max(int(b0[k]), int(absA[k].sum()) - int(b0[k])) for k in range(m)]
+        e_rest = 256 * s_g * s_g * prof_max + s_f * pq * sum(g * g + int(bk) * int(bk) for g, bk in zip(gk, b0))
+        e_lam = s_f * s_g * sum(g + int(bk) for g, bk in zip(gk, b0))
+        room = (ZBUDGET >> u) - e_rest
+        if room <= 0:
+            raise OracleRangeError("parallel tempering energies exceed the 2^61 budget")
+        if e_lam > 0:
+            lq_max = min(lq_max, room // e_lam)
+        if lq_max < 256:
+            raise OracleRangeError("multiplier range below 1.0")
+
     # diminishing multiplier step eta H / (H + k) (Sec. III-A's surrogate
     # subgradient ascent converges under such steps); k is capped where the
     # exact step's denominator eta_den R s_g (H + k) would reach 2^62
@@ -226,14 +279,15 @@ def build_program(prob: Problem, par: Params) -> Program:
         raise ValueError("eta_decay must lie in [0, 2^20]")
     kcap = 0
     if H > 0:
-        lam_den = Fraction(par.eta).denominator * int(par.replicas) * s_g
+        samples = int(par.replicas) // L if L else int(par.replicas)
+        lam_den = Fraction(par.eta).denominator * samples * s_g
         kcap = min(((1 << 62) - 1) // lam_den - H, (1 << 31) - 1)
         if kcap < 1:
             raise OracleRangeError("diminishing step exceeds 64-bit bounds")
 
     return Program(prob.kind, n, m, n_ext, Q, slack, W, h, A, b0.copy(), s_f, s_g, D, pq, T, S,
                    B, lq_max, Fraction(par.eta), int(par.replicas), int(par.seed),
-                   int(par.instance_id), H, kcap)
+                   int(par.instance_id), H, kcap, L, Bl)
 
 
 # ---------------------------------------------------------------------------
@@ -292,7 +346,7 @@ def step_size(prog: Program, k: int) -> Fraction:
 def lambda_step(prog: Program, lam_acc: list, G: list, R: int | None = None, k: int = 0):
     """lam_acc on a 2^-32 grid of lambda_n; returns (new lam_acc, lq on 2^-8 grid).
     k is the index of the round whose residual sums G are (it sets the step size)."""
-    R = prog.R if R is None else R
+    R = prog.samples if R is None else R
     cap = prog.lq_max << 24
     eta = step_size(prog, k)
     new_acc, lq = [], []
@@ -355,6 +409,13 @@ def _lib():
     lib.oracle_index.restype = ctypes.c_int32
     lib.oracle_philox.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_philox.restype = None
+    lib.oracle_pt_round.argtypes = [ctypes.POINTER(_Prog), ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    lib.oracle_pt_round.restype = ctypes.c_int
+    lib.oracle_energy_words.argtypes = [ctypes.POINTER(_Prog), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+    lib.oracle_energy_words.restype = None
     return lib
 
 
@@ -381,6 +442,17 @@ def philox(ctr, key) -> list:
     out = np.zeros(4, dtype=np.uint32)
     _lib().oracle_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
     return [int(v) for v in out]
+
+
+def energy_c(prog: Program, x, lq) -> int:
+    """The C core's D L_n(x) (what the parallel-tempering exchange compares)."""
+    cp = _CProg(prog)
+    xb = np.ascontiguousarray(np.array(x, dtype=np.uint8))
+    l = np.ascontiguousarray(np.array(lq, dtype=np.int32).reshape(prog.m))
+    hi = ctypes.c_int64()
+    lo = ctypes.c_uint64()
+    _lib().oracle_energy_words(ctypes.byref(cp.s), xb.ctypes.data, l.ctypes.data, ctypes.byref(hi), ctypes.byref(lo))
+    return (int(hi.value) << 64) + int(lo.value)
 
 
 def local_field(prog: Program, x, lq, i: int) -> int:
@@ -414,6 +486,29 @@ def sa_round(prog: Program, lq, k: int, r0: int = 0, nrep: int | None = None,
     return x, g[:, :prog.m]
 
 
+def pt_round(prog: Program, lq, k: int, c0: int = 0, nchains: int | None = None,
+             nthreads: int | None = None):
+    """Parallel tempering round k for chains c0 .. c0+nchains-1 (replicas
+    c0 L .. ): final states (nrep, n_ext), residuals (nrep, m) and final ladder
+    positions (nrep,); the chain's sample is the replica at position L - 1."""
+    L = prog.pt_slots
+    nchains = prog.R // L - c0 if nchains is None else int(nchains)
+    nthreads = (os.cpu_count() or 1) if nthreads is None else int(nthreads)
+    cp = _CProg(prog)
+    l = np.ascontiguousarray(np.array(lq, dtype=np.int32).reshape(prog.m))
+    Bl = np.ascontiguousarray(np.array(prog.Bl, dtype=np.int64))
+    X = np.ascontiguousarray(np.array(exchange_table(), dtype=np.int32))
+    nrep = nchains * L
+    x = np.zeros((nrep, prog.n_ext), dtype=np.uint8)
+    g = np.zeros((nrep, max(prog.m, 1)), dtype=np.int64)
+    slot = np.zeros(nrep, dtype=np.int32)
+    rc = _lib().oracle_pt_round(ctypes.byref(cp.s), l.ctypes.data, int(k), L, Bl.ctypes.data, X.ctypes.data,
+                                int(c0), nchains, x.ctypes.data, g.ctypes.data, slot.ctypes.data, nthreads)
+    if rc != 0:
+        raise RuntimeError("oracle_pt_round failed")
+    return x, g[:, :prog.m], slot
+
+
 # ---------------------------------------------------------------------------
 # best feasible sample (Algorithm 1: keep the feasible samples, return the best)
 
@@ -434,7 +529,9 @@ def saim(prob: Problem, par: Params, rounds: int, lq0=None, nthreads: int | None
          keep_states: bool = True):
     """Algorithm 1 with R replicas per round.  Returns a dict with per-round
     multipliers used, per-replica final states / residuals / profits /
-    feasibility, and the best feasible (profit, round, replica, x)."""
+    feasibility, and the best feasible (profit, round, replica, x).  With
+    parallel tempering the IM's samples are the chains' coldest replicas: the
+    residual sums, the feasible count and the best record take those only."""
     prog = build_program(prob, par)
     lq = [0] * prog.m if lq0 is None else [int(v) for v in lq0]
     lq = [max(-prog.lq_max, min(prog.lq_max, v)) for v in lq]
@@ -444,13 +541,18 @@ def saim(prob: Problem, par: Params, rounds: int, lq0=None, nthreads: int | None
     best = None
     log = []
     for k in range(rounds):
-        x, g = sa_round(prog, lq, k, 0, prog.R, nthreads)
+        if prog.pt_slots:
+            x, g, slot = pt_round(prog, lq, k, 0, None, nthreads)
+            sample = slot == prog.pt_slots - 1
+        else:
+            x, g = sa_round(prog, lq, k, 0, prog.R, nthreads)
+            slot, sample = None, np.ones(prog.R, dtype=bool)
         profit, feas = score(prog, x)
-        best = best_update(best, k, profit, feas, x[:, :prog.n])
-        G = [int(v) for v in g.sum(axis=0)]
-        entry = {"lq": list(lq), "G": G, "feasible": int(feas.sum()), "sat": sat}
+        best = best_update(best, k, profit, feas & sample, x[:, :prog.n])
+        G = [int(v) for v in g[sample].sum(axis=0)]
+        entry = {"lq": list(lq), "G": G, "feasible": int((feas & sample).sum()), "sat": sat}
         if keep_states:
-            entry.update(x=x, g=g, profit=profit, feasible_mask=feas)
+            entry.update(x=x, g=g, profit=profit, feasible_mask=feas, slot=slot, sample=sample)
         log.append(entry)
         acc, lq = lambda_step(prog, acc, G, k=k)
         sat = saturation_mask(acc, cap, sat)

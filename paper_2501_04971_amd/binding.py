@@ -42,7 +42,7 @@ class pbit_params(ctypes.Structure):
                 ("p_q", ctypes.c_int32), ("alpha_num", ctypes.c_int32),
                 ("alpha_den", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("instance_id", ctypes.c_uint32), ("fixed_beta", ctypes.c_int32),
-                ("eta_decay_rounds", ctypes.c_int32)]
+                ("eta_decay_rounds", ctypes.c_int32), ("pt_slots", ctypes.c_int32)]
 
 
 class pbit_batch_layout(ctypes.Structure):
@@ -69,7 +69,7 @@ class pbit_plan_info(ctypes.Structure):
                 ("out_profit", ctypes.c_size_t), ("out_feasible", ctypes.c_size_t),
                 ("out_G", ctypes.c_size_t), ("out_lambda", ctypes.c_size_t),
                 ("out_round", ctypes.c_size_t), ("out_sat", ctypes.c_size_t),
-                ("out_bytes", ctypes.c_size_t)]
+                ("out_slot", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t)]
 
 
 EXPORTS = {
@@ -91,6 +91,7 @@ EXPORTS = {
     "pbit_destroy_instance": (ctypes.c_int, [ctypes.c_void_p]),
     "pbit_last_error": (ctypes.c_char_p, []),
     "pbit_theta_table": (ctypes.c_int, [ctypes.c_void_p]),
+    "pbit_exchange_table": (ctypes.c_int, [ctypes.c_void_p]),
     "pbit_instance_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "pbit_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
@@ -181,7 +182,7 @@ class _Marshalled:
                                   -1 if par.p_q is None else int(par.p_q), an, ad,
                                   int(par.seed) & ((1 << 64) - 1),
                                   int(par.instance_id) & 0xFFFFFFFF, 1 if par.fixed_beta else 0,
-                                  int(par.eta_decay))
+                                  int(par.eta_decay), int(getattr(par, "pt_slots", 0)))
 
 
 def pbit_plan(prob: Problem, par: Params) -> pbit_plan_info:
@@ -199,6 +200,12 @@ def pbit_workspace_bytes(prob: Problem, par: Params) -> int:
 def pbit_theta_table() -> np.ndarray:
     out = np.zeros(THETA_LEN, dtype=np.int32)
     _check(lib().pbit_theta_table(out.ctypes.data))
+    return out
+
+
+def pbit_exchange_table() -> np.ndarray:
+    out = np.zeros(THETA_LEN, dtype=np.int32)
+    _check(lib().pbit_exchange_table(out.ctypes.data))
     return out
 
 
@@ -410,6 +417,7 @@ class Instance:
             "lambda_q": view(i.out_lambda, np.int32, m).copy(),
             "round": int(view(i.out_round, np.int32, 1)[0]),
             "lambda_saturated": int(view(i.out_sat, np.uint32, 1)[0]),
+            "slot": view(i.out_slot, np.int32, R).copy(),
         }
 
     def close(self):

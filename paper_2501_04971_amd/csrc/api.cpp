@@ -126,6 +126,21 @@ int bit_length(int64_t v)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Threshold table: round(2^24 / (1 + exp(-2 j / 256))) in 80-bit long double.
+// X[i] = round(2^24 exp((i - 4608) / 256)): the Metropolis acceptance of a
+// replica exchange on the 2^-8 grid of its exponent.
+bool make_exchange_table(std::vector<int32_t> &x)
+{
+    x.resize(kXLen);
+    for (int i = 0; i < kXLen; ++i) {
+        const long double v = 16777216.0L * expl((long double)(i - (kXLen - 1)) / 256.0L);
+        const long double fl = floorl(v);
+        const long double fr = v - fl;
+        if (i != kXLen - 1 && fabsl(fr - 0.5L) < 1e-9L) return false;  // too close to a tie to trust
+        x[i] = (int32_t)fl + (fr > 0.5L ? 1 : 0);
+    }
+    return true;
+}
+
 bool make_theta(std::vector<int32_t> &t)
 {
     t.resize(kThetaLen);
@@ -140,9 +155,9 @@ bool make_theta(std::vector<int32_t> &t)
 }
 
 struct Layout {
-    size_t theta, btab, zsweep, J, acol, kbase, sa2, b, hprof, slack_off, slack_q;  // constants
+    size_t theta, btab, zsweep, bladder, xtab, J, acol, kbase, sa2, b, hprof, slack_off, slack_q;  // constants
     size_t kconst /* per-site records */, lam_acc, lam_q, round_k, G, best, best_x, feas;          // state
-    size_t rx, rg, rprofit, rfeas;                                         // outputs
+    size_t rx, rg, rprofit, rfeas, rslot;                                  // outputs
     size_t upload_end, total;
 };
 
@@ -155,12 +170,16 @@ struct Plan {
     int64_t irnd = 0;
     int64_t sfsg = 0, eta_num = 0, lam_den = 1;
     int32_t eta_h = 0, eta_kcap = 0;
+    int pt = 0;                    // parallel tempering chain length L (0: annealing)
+    int samples = 0;               // samples per round the multiplier step averages (R, or R / L)
     int n_rec = 0;                 // per-site records (padding included)
     std::vector<int64_t> site;     // [n_rec][4]: K0, K1 (filled on the device), c, meta
     uint64_t seed = 0;
     uint32_t inst = 0;
     std::vector<int32_t> theta, btab, acol, hprof, slack_off, slack_q;
     std::vector<ZtSweep> zsweep;   // [T] field-threshold constants of the split kernels
+    std::vector<int32_t> bladder;  // [64] parallel tempering ladder on the beta grid (first pt used)
+    std::vector<int32_t> xtab;     // [kXLen] exchange acceptance 2^24 exp(j / 256), j = -4608 .. 0
     std::vector<int64_t> kbase, sa2, b;
     std::vector<int8_t> J;  // n_pad x (n_pad + 16)
     Layout L{};
@@ -182,6 +201,14 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
         return fail(PBIT_EINVAL, "alpha must be a non-negative rational");
     if (p->kind == PBIT_QKP && par->p_q == -1 && (p->density_num < 0 || p->density_den < 1))
         return fail(PBIT_EINVAL, "density must be a non-negative rational");
+    if (par->pt_slots != 0) {
+        const int L = par->pt_slots;
+        if (p->kind != PBIT_QKP) return fail(PBIT_EINVAL, "parallel tempering is built for the quadratic kernel");
+        if (L < 2 || L > 64 || 64 % L != 0 || par->replicas % L != 0)
+            return fail(PBIT_EINVAL, "pt_slots must divide 64 and the replica count, and be >= 2");
+        if (par->beta_num == 0 || par->fixed_beta)
+            return fail(PBIT_EINVAL, "parallel tempering needs beta_max > 0 and no fixed-beta mode");
+    }
 
     const int n = p->n, m = p->m;
     P.kind = p->kind;
@@ -191,6 +218,8 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     P.R = par->replicas;
     P.seed = par->seed;
     P.inst = par->instance_id;
+    P.pt = par->pt_slots;
+    P.samples = P.pt ? P.R / P.pt : P.R;
 
     // item data
     std::vector<int64_t> h(n, 0);
@@ -335,9 +364,10 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     const i128 k2 = (i128)2 * P.s_f * P.pq;
     P.sfsg = P.s_f * P.s_g;
 
-    // multiplier step: acc += round(2^32 eta_num G / (eta_den R s_g)), G <= R gmax
-    const i128 lam_den = (i128)par->eta_den * P.R * P.s_g;
-    if ((i128)par->eta_num * P.R * gmax >= ((i128)1 << 62) || lam_den >= ((i128)1 << 62))
+    // multiplier step: acc += round(2^32 eta_num G / (eta_den R' s_g)), G <= R' gmax, R'
+    // the samples per round
+    const i128 lam_den = (i128)par->eta_den * P.samples * P.s_g;
+    if ((i128)par->eta_num * P.samples * gmax >= ((i128)1 << 62) || lam_den >= ((i128)1 << 62))
         return fail(PBIT_ERANGE, "multiplier step exceeds 64-bit bounds");
     if (((i128)par->eta_num * gmax << 32) >= ((i128)1 << 62) * par->eta_den * P.s_g)
         return fail(PBIT_ERANGE, "multiplier step too large");
@@ -348,7 +378,7 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
         return fail(PBIT_EINVAL, "eta_decay_rounds must lie in [0, 2^20]");
     P.eta_h = par->eta_decay_rounds;
     if (P.eta_h > 0) {
-        if ((i128)par->eta_num * P.R * gmax * P.eta_h >= ((i128)1 << 62))
+        if ((i128)par->eta_num * P.samples * gmax * P.eta_h >= ((i128)1 << 62))
             return fail(PBIT_ERANGE, "diminishing multiplier step exceeds 64-bit bounds");
         const i128 kc = (((i128)1 << 62) - 1) / lam_den - P.eta_h;
         if (kc < 1) return fail(PBIT_ERANGE, "diminishing multiplier step exceeds 64-bit bounds");
@@ -423,6 +453,33 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
         P.hchi = INT32_MAX;
     }
 
+    // parallel tempering: ladder beta_max (j + 1) / L on the beta grid, exchange
+    // table, and the multiplier range narrowed so that every energy difference
+    // D (L(x) - L(0)), carried as 2^u, stays below 2^61
+    P.bladder.assign(64, 0);
+    P.xtab.assign(kXLen, 0);
+    if (P.pt) {
+        const u128 den = (u128)2 * P.s_f * (u128)sg2;
+        for (int j = 0; j < P.pt; ++j)
+            P.bladder[j] = (int32_t)round_shifted((u128)par->beta_num * (u128)(j + 1), P.S,
+                                                  den * (u128)par->beta_den * (u128)P.pt);
+        if (!make_exchange_table(P.xtab)) return fail(PBIT_ERANGE, "exchange table rounding undecidable");
+        i128 prof = 0;
+        for (int i = 0; i < n; ++i) prof += std::llabs(h[i]);
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) prof += std::llabs(W[(size_t)i * n + j]);
+        i128 sq = 0, lin = 0;
+        for (int k = 0; k < m; ++k) {
+            sq += (i128)gmk[k] * gmk[k] + (i128)P.b[k] * P.b[k];
+            lin += (i128)gmk[k] + P.b[k];
+        }
+        const i128 room = (kZBudget >> zsh) - ((i128)256 * sg2 * prof + (i128)P.s_f * P.pq * sq);
+        if (room <= 0) return fail(PBIT_ERANGE, "parallel tempering energies exceed the 2^61 budget");
+        const i128 lam = (i128)P.s_f * P.s_g * lin;
+        if (lam > 0) P.lq_max = (int64_t)std::min<i128>(P.lq_max, room / lam);
+        if (P.lq_max < 256) return fail(PBIT_ERANGE, "multiplier range below 1.0");
+    }
+
     // per-site records: c_i = change of Z_i when the preceding visit (site i-1)
     // goes 0 -> 1; meta = (a_i, -1 for a site the loop visits, 0 for padding)
     P.site.assign((size_t)P.n_rec * 4, 0);
@@ -488,6 +545,8 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     L.theta = put(kThetaLen * 4);
     L.btab = put((size_t)P.T * 4);
     L.zsweep = put((size_t)P.T * sizeof(ZtSweep));
+    L.bladder = put(64 * 4);
+    L.xtab = put((size_t)kXLen * 4);
     L.J = put(P.J.size());
     L.acol = put(P.acol.size() * 4);
     L.kbase = put((size_t)n_ext * 8);
@@ -509,6 +568,7 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     L.rg = put((size_t)P.R * m * 4);
     L.rprofit = put((size_t)P.R * 8);
     L.rfeas = put((size_t)P.R * 4);
+    L.rslot = put((size_t)P.R * 4);
     L.total = o;
     return PBIT_OK;
 }
@@ -542,6 +602,7 @@ void fill_plan_info(const Plan &P, pbit_plan_info *out)
     out->out_lambda = put((size_t)P.m * 4);
     out->out_round = put(4);
     out->out_sat = put(4);
+    out->out_slot = put((size_t)P.R * 4);
     out->out_bytes = o;
 }
 
@@ -670,6 +731,8 @@ pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *
     cp(L.theta, P.theta.data(), P.theta.size() * 4);
     cp(L.btab, P.btab.data(), P.btab.size() * 4);
     cp(L.zsweep, P.zsweep.data(), P.zsweep.size() * sizeof(ZtSweep));
+    cp(L.bladder, P.bladder.data(), P.bladder.size() * 4);
+    cp(L.xtab, P.xtab.data(), P.xtab.size() * 4);
     cp(L.J, P.J.data(), P.J.size());
     cp(L.acol, P.acol.data(), P.acol.size() * 4);
     cp(L.kbase, P.kbase.data(), P.kbase.size() * 8);
@@ -688,6 +751,10 @@ pbit_status create_impl(const pbit_problem *prob, const pbit_params *par, void *
     d.theta = reinterpret_cast<const int32_t *>(base + L.theta);
     d.Btab = reinterpret_cast<const int32_t *>(base + L.btab);
     d.zsweep = reinterpret_cast<const ZtSweep *>(base + L.zsweep);
+    d.bladder = reinterpret_cast<const int32_t *>(base + L.bladder);
+    d.xtab = reinterpret_cast<const int32_t *>(base + L.xtab);
+    d.rslot = reinterpret_cast<int32_t *>(base + L.rslot);
+    d.pt = P.pt;
     d.acol = reinterpret_cast<const int32_t *>(base + L.acol);
     d.kbase = reinterpret_cast<const int64_t *>(base + L.kbase);
     d.sa2 = reinterpret_cast<const int64_t *>(base + L.sa2);
@@ -790,6 +857,7 @@ pbit_status batch_sizes(const pbit_problem *probs, const pbit_params *params, in
             g_error = "member " + std::to_string(i) + ": " + g_error;
             return st;
         }
+        if (P.pt) return fail(PBIT_EINVAL, "member " + std::to_string(i) + ": parallel tempering runs as single instances");
         if (batch_variant_code(P.variant, P.nb, P.m) < 0 ||
             (P.variant != kQuad && resident_bytes(P, 4) > kMaxLds))
             return fail(PBIT_ERANGE, "member " + std::to_string(i) + ": no batch body for this instance shape");
@@ -956,6 +1024,15 @@ pbit_status pbit_theta_table(int32_t *theta)
     return PBIT_OK;
 }
 
+pbit_status pbit_exchange_table(int32_t *x)
+{
+    if (!x) return fail(PBIT_EINVAL, "null output");
+    std::vector<int32_t> t;
+    if (!make_exchange_table(t)) return fail(PBIT_ERANGE, "exchange table rounding undecidable");
+    std::memcpy(x, t.data(), t.size() * 4);
+    return PBIT_OK;
+}
+
 pbit_status pbit_plan(const pbit_problem *prob, const pbit_params *par, pbit_plan_info *out)
 {
     if (!out) return fail(PBIT_EINVAL, "null output");
@@ -1022,7 +1099,9 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
     hipError_t e;
     switch (inst->plan.variant) {
         case kQuad: {
-            const bool pc = inst->split >= 1 || (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus);
+            // parallel tempering runs in the plain kernel (every lane its own temperature)
+            const bool pc = d.pt == 0 &&
+                            (inst->split >= 1 || (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus));
             // six producers (two waves per SIMD) pay off for instances of few
             // blocks (measured: 4 blocks faster, 10 blocks slower than three)
             const int producers = inst->split == 2 || (inst->split < 0 && inst->plan.nb <= 4) ? 6 : 3;
@@ -1134,6 +1213,7 @@ pbit_status pbit_round_outputs(pbit_instance *inst, void *dev_out, size_t bytes,
         {info.out_profit, d.rprofit, (size_t)P.R * 8}, {info.out_feasible, d.rfeas, (size_t)P.R * 4},
         {info.out_G, d.G, (size_t)P.m * 8},            {info.out_lambda, d.lam_q, (size_t)P.m * 4},
         {info.out_round, d.round_k, 4},                {info.out_sat, d.lam_sat, 4},
+        {info.out_slot, d.rslot, (size_t)P.R * 4},
     };
     for (const Piece &pc : pieces) {
         hipError_t e = hipMemcpyAsync(o + pc.off, pc.src, pc.bytes, hipMemcpyDeviceToDevice, s);

@@ -8,6 +8,7 @@ namespace pbit {
 constexpr int kThetaHalf = 2304;
 constexpr int kThetaLen = 2 * kThetaHalf + 1;
 constexpr int kThetaBytes = 18448;          // kThetaLen * 4 rounded up to 16 bytes
+constexpr int kXLen = 4609;                 // replica-exchange table: exp(j / 256), j = -4608 .. 0
 constexpr int kMaxM = 32;                   // constraints per instance
 constexpr int kMaxQuadBlocks = 11;          // quadratic kernel: n_ext <= 352
 constexpr int kMaxWords = 64;               // linear kernel: n_ext <= 2048
@@ -37,6 +38,8 @@ struct DevInstance {
     const int32_t *theta;     // [kThetaLen]
     const int32_t *Btab;      // [T] beta grid
     const ZtSweep *zsweep;    // [T] constants of the field thresholds (split kernels)
+    const int32_t *bladder;   // [64] parallel tempering ladder on the beta grid
+    const int32_t *xtab;      // [4609] exchange acceptance 2^24 exp(j / 256), j = -4608 .. 0
     const int32_t *acol;      // [n_ext][m] extended constraint coefficients, site-major
     const int64_t *kbase;     // [n_ext] 256 s_g^2 h_i - Sa_i
     const int64_t *sa2;       // [n_ext] 2 Sa_i,  Sa_i = s_f Pq |a_i|^2
@@ -60,6 +63,7 @@ struct DevInstance {
     int32_t *rg;              // [R][m]
     int64_t *rprofit;         // [R]
     int32_t *rfeas;           // [R]
+    int32_t *rslot;           // [R] final ladder position (parallel tempering; 0 otherwise)
     // scalars
     int32_t n, m, n_ext, n_pad, words, owords, R, T, S, nq;
     int32_t sg2;              // 2^u s_g^2 (quadratic kernel; < 2^31)
@@ -75,7 +79,7 @@ struct DevInstance {
     uint32_t seed_lo, seed_hi, inst_id;
     int32_t eta_h;            // diminishing step eta H / (H + k); 0: constant eta
     int32_t eta_kcap;         // largest k used in H + k (keeps lam_den (H + k) < 2^62)
-    int32_t pad0;
+    int32_t pt;               // parallel tempering chain length L (0: annealing)
 };
 
 // Per-site record (4 x int64), i < n_pad:

@@ -30,8 +30,11 @@ __device__ __forceinline__ void round_reduce_body(const DevInstance &d)
     int64_t bp = INT64_MIN;
     int32_t br = INT32_MAX;
     int32_t nf = 0;
+    // the round's samples: every replica's final state, or with parallel
+    // tempering each chain's replica at the coldest ladder position
     for (int r = tid; r < d.R; r += kReduceThreads) {
-        if (d.rfeas[r]) {
+        if (d.pt == 0) d.rslot[r] = 0;
+        if (d.rfeas[r] && (d.pt == 0 || d.rslot[r] == d.pt - 1)) {
             ++nf;
             const int64_t p = d.rprofit[r];
             if (better(p, r, bp, br)) {
@@ -64,7 +67,8 @@ __device__ __forceinline__ void round_reduce_body(const DevInstance &d)
     // residual sums, one constraint at a time
     for (int c = 0; c < d.m; ++c) {
         int64_t s = 0;
-        for (int r = tid; r < d.R; r += kReduceThreads) s += d.rg[(int64_t)r * d.m + c];
+        for (int r = tid; r < d.R; r += kReduceThreads)
+            if (d.pt == 0 || d.rslot[r] == d.pt - 1) s += d.rg[(int64_t)r * d.m + c];
         sg[tid] = s;
         __syncthreads();
         for (int h = kReduceThreads / 2; h > 0; h >>= 1) {

@@ -118,6 +118,7 @@ struct BlockVisit {
     uint32_t thA, thB, pend;
     int32_t g;
     int32_t Bt, ish, hclo, hchi;
+    int64_t E;               // parallel tempering: D (L(x) - L(0)) carried as 2^u
     int64_t irnd, sg2, k2;
     uint32_t cbase, kround, inst, seed_lo, seed_hi;
     uint64_t m2;
@@ -189,8 +190,10 @@ __device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8], con
 }
 
 // One visit of site s without lookahead: its threshold is computed from the
-// current state right before the decision.
-template <int s, int LS, int WPB>
+// current state right before the decision.  With parallel tempering the
+// replica's energy follows every flip: Z is -D times the energy change of
+// switching the site on, so a flip by delta changes D L by -delta Z.
+template <int s, int LS, int WPB, bool PT = false>
 __device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8])
 {
     stream_slab<s, (LS - 16) / 32, WPB>(v);
@@ -213,6 +216,7 @@ __device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[
     xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
     v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
     v.g += __mul24(delta, (int32_t)meta);
+    if constexpr (PT) v.E = delta > 0 ? v.E - Z : (delta < 0 ? v.E + Z : v.E);
 }
 
 #ifndef PBIT_SCHED_WINDOW
@@ -228,20 +232,68 @@ __device__ __forceinline__ void visit_fence()
     if constexpr ((s + 1) % PBIT_SCHED_WINDOW == 0) __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int LS, int WPB, bool LA, int... S>
+template <int LS, int WPB, bool LA, bool PT, int... S>
 __device__ __forceinline__ void visit_block(BlockVisit &v, uint32_t (&xc)[8], std::integer_sequence<int, S...>)
 {
     const uint32_t x0[8] = {xc[0], xc[1], xc[2], xc[3], xc[4], xc[5], xc[6], xc[7]};
     if constexpr (LA)
         ((visit_site<S, LS, WPB>(v, xc, x0), visit_fence<S>()), ...);
     else
-        ((visit_site_direct<S, LS, WPB>(v, xc, x0), visit_fence<S>()), ...);
+        ((visit_site_direct<S, LS, WPB, PT>(v, xc, x0), visit_fence<S>()), ...);
+}
+
+// Replica exchange after sweep t (parallel tempering, chains of L lanes inside
+// a wave, L a power of two dividing 64).  Lane l of a chain is the keeper of
+// ladder position tau = l mod L: it knows `owner`, the lane whose replica is at
+// tau.  For the pairs (tau, tau + 1) with tau = t mod 2 the keeper of tau draws
+// from Philox(t, k | 2^31, r, instance), r its own replica index (= c L + tau),
+// and decides: swap when j = floor(2 (B_tau - B_tau+1)(E_a - E_b) / 2^S') >= 0
+// or u24 < X[j] (j >= -4608, X[j] = 2^24 exp(j / 256)), E the carried energies
+// of the replicas a at tau and b at tau + 1, S' = ish + 32.  The keepers then
+// take their new owners and every replica learns its new position.
+__device__ __forceinline__ void pt_exchange(const DevInstance &d, int t, uint32_t kround, uint64_t m2, int64_t E,
+                                            int32_t &owner, int32_t &slot)
+{
+    const int L = d.pt;
+    const int lane = threadIdx.x & 63;
+    const int tau = lane & (L - 1);
+    const int up = tau + 1 < L ? lane + 1 : lane;  // keeper of tau + 1
+    const int32_t own_lo = owner;
+    const int32_t own_hi = __shfl(owner, up, 64);
+    const int32_t elo_l = __shfl((int32_t)(uint32_t)E, own_lo, 64), elo_h = __shfl((int32_t)(E >> 32), own_lo, 64);
+    const int32_t ehi_l = __shfl((int32_t)(uint32_t)E, own_hi, 64), ehi_h = __shfl((int32_t)(E >> 32), own_hi, 64);
+    const int64_t ea = (int64_t)(((uint64_t)(uint32_t)elo_h << 32) | (uint32_t)elo_l);
+    const int64_t eb = (int64_t)(((uint64_t)(uint32_t)ehi_h << 32) | (uint32_t)ehi_l);
+    const bool pair = (tau & 1) == (t & 1) && tau + 1 < L;
+    bool accept = false;
+    if (pair) {
+        // (B_tau - B_tau+1)(E_a - E_b) = (B_tau+1 - B_tau)(E_b - E_a), the first
+        // factor in [0, 2^31) and |E_b - E_a| < 2^62
+        const int32_t dB = d.bladder[tau + 1] - d.bladder[tau];
+        const int64_t hq = field_hi(eb - ea, dB, 0);  // floor(dB dE / 2^32)
+        const int64_t j = hq >> (d.ish - 1);            // floor(2 dB dE / 2^S')
+        if (j >= 0) {
+            accept = true;
+        } else {
+            uint32_t w[4];
+            philox_block((uint32_t)t, kround | 0x80000000u, m2, d.inst_id, d.seed_lo, d.seed_hi, w);
+            const int idx = j < -(kXLen - 1) ? 0 : (int)j + kXLen - 1;
+            accept = (w[0] >> 8) < (uint32_t)d.xtab[idx];
+        }
+    }
+    // the keeper of tau + 1 takes the lower replica when the pair below swapped
+    const int down = tau > 0 ? lane - 1 : lane;
+    const int acc_below = __shfl(accept ? 1 : 0, down, 64) & (tau > 0 ? 1 : 0);
+    const int32_t own_below = __shfl(own_lo, down, 64);
+    owner = accept ? own_hi : (acc_below ? own_below : own_lo);
+    // every replica's position: the keeper of tau pushes tau to its owner's lane
+    slot = __builtin_amdgcn_ds_permute(owner << 2, tau);
 }
 
 // One annealing run (T sweeps) of the replicas rbase + [0, 64 WPB) of instance
 // d, followed by the scoring of the final states.  The workgroup has WPB
 // waves; smem must hold quad_lds_bytes<NB>() bytes.
-template <int NB, int WPB, bool LA>
+template <int NB, int WPB, bool LA, bool PT = false>
 __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsigned char *smem)
 {
     constexpr int NP = NB * 32;        // padded spin count
@@ -265,7 +317,6 @@ __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsign
     const uint32_t kround = (uint32_t)d.round_k[0];
     const uint64_t m2 = (uint64_t)0xCD9E8D57u * (uint32_t)r;
     const int32_t *__restrict__ Btab = d.Btab;
-    (void)lane;
 
     uint32_t x[NB][8];
 #pragma unroll
@@ -291,12 +342,17 @@ __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsign
     v.nw = WPB;
 #pragma unroll
     for (int w = 0; w < 4; ++w) v.rnd[w] = 0u;
+    // parallel tempering: the replica's ladder position, the lane this lane
+    // keeps track of (the one at ladder position lane mod L), its energy
+    int32_t slot = 0, owner = lane;
+    v.E = 0;
+    if constexpr (PT) slot = lane & (d.pt - 1);
 
     // the two LDS slab buffers alternate every block; the block sequence wraps
     // from NB - 1 to 0 at each sweep, so the buffer index is a running toggle
     int buf = 0;
     for (int t = 0; t < d.T; ++t) {
-        v.Bt = Btab[t];
+        v.Bt = PT ? d.bladder[slot] : Btab[t];
         v.cbase = (uint32_t)t * (uint32_t)d.nq;
         for (int blk = 0; blk < NB; ++blk) {
             const int8_t *slab = slabs + buf * SLAB;
@@ -321,13 +377,14 @@ __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsign
                 v.thB = v.thA;
                 v.pend = 0u;
             }
-            visit_block<LS, WPB, LA>(v, x[0], std::make_integer_sequence<int, 32>{});
+            visit_block<LS, WPB, LA, PT>(v, x[0], std::make_integer_sequence<int, 32>{});
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             rotate_chunks<NB>(x);
             buf ^= 1;
             __syncthreads();
         }
+        if constexpr (PT) pt_exchange(d, t, kround, m2, v.E, owner, slot);
     }
 
     // Score the final state: profit = (sum_{i<n} x_i (2 h_i + F_i)) / 2 with
@@ -368,6 +425,7 @@ __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsign
         d.rprofit[r] = pacc / 2;
         d.rfeas[r] = v.g <= sval ? 1 : 0;
         d.rg[r] = v.g;
+        if constexpr (PT) d.rslot[r] = slot;
     }
 }
 

@@ -3,18 +3,21 @@
 
 namespace pbit {
 
-template <int NB, int WPB>
+template <int NB, int WPB, bool PT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sweep_quad(const DevInstance d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    quad_run<NB, WPB, false>(d, blockIdx.x * WPB * kWave, smem);
+    quad_run<NB, WPB, false, PT>(d, blockIdx.x * WPB * kWave, smem);
 }
 
-#define PBIT_QUAD_CASE(nb)                                                                  \
-    case nb:                                                                                \
-        kern = wpb == 1 ? reinterpret_cast<const void *>(&sweep_quad<nb, 1>)                \
-                        : reinterpret_cast<const void *>(&sweep_quad<nb, 4>);               \
-        lds = quad_lds_bytes<nb>();                                                         \
+// PT: parallel tempering instead of annealing (d.pt > 0)
+#define PBIT_QUAD_CASE(nb)                                                                          \
+    case nb:                                                                                        \
+        kern = pt ? (wpb == 1 ? reinterpret_cast<const void *>(&sweep_quad<nb, 1, true>)             \
+                              : reinterpret_cast<const void *>(&sweep_quad<nb, 4, true>))            \
+                  : (wpb == 1 ? reinterpret_cast<const void *>(&sweep_quad<nb, 1, false>)            \
+                              : reinterpret_cast<const void *>(&sweep_quad<nb, 4, false>));          \
+        lds = quad_lds_bytes<nb>();                                                                 \
         break;
 
 // waves_per_block: 1 or 4 (other values round to 4)
@@ -23,6 +26,7 @@ hipError_t launch_sweep_quad(const DevInstance &d, int nb, int waves_per_block, 
     const void *kern = nullptr;
     size_t lds = 0;
     const int wpb = waves_per_block == 1 ? 1 : 4;
+    const bool pt = d.pt > 0;
     switch (nb) {
         PBIT_QUAD_CASE(1) PBIT_QUAD_CASE(2) PBIT_QUAD_CASE(3) PBIT_QUAD_CASE(4) PBIT_QUAD_CASE(5)
         PBIT_QUAD_CASE(6) PBIT_QUAD_CASE(7) PBIT_QUAD_CASE(8) PBIT_QUAD_CASE(9) PBIT_QUAD_CASE(10)

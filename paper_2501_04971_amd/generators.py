@@ -71,6 +71,8 @@ class Params:
     instance_id  last Philox counter word (tells instances of a batch apart)
     fixed_beta   hold beta at beta_max for every sweep (test mode)
     eta_decay    H: diminishing step eta H / (H + k) after round k; 0 = constant
+    pt_slots     L > 0: parallel tempering instead of annealing, chains of L
+                 replicas at the fixed ladder beta_max (j + 1) / L, j < L
     """
 
     replicas: int = 64
@@ -83,6 +85,7 @@ class Params:
     instance_id: int = 0
     fixed_beta: bool = False
     eta_decay: int = 0
+    pt_slots: int = 0
 
 
 def rng_for(family: int, index: int) -> np.random.Generator:

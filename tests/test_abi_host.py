@@ -64,6 +64,7 @@ def test_plan_matches_oracle_program(lib, case):
 
 def test_theta_table_matches_oracle(lib):
     assert B.pbit_theta_table().tolist() == list(O.theta_table())
+    assert B.pbit_exchange_table().tolist() == list(O.exchange_table())
 
 
 def _expect(status, prob, par):
@@ -161,3 +162,24 @@ def test_diminishing_step_settings_are_validated(lib):
         _expect(B.PBIT_EINVAL, prob, G.Params(replicas=64, sweeps=10, eta_decay=bad))
     for ok in (0, 1, 1 << 20):
         B.pbit_plan(prob, G.Params(replicas=64, sweeps=10, eta_decay=ok))
+
+
+def test_parallel_tempering_settings_and_plan(lib):
+    """pt_slots: refused where the oracle refuses it; the multiplier range is
+    the oracle's (narrowed for the exchange's energies); the round outputs
+    carry the ladder positions."""
+    prob = G.qkp(40, Fraction(1, 2), G.rng_for(962, 0))
+    for bad in (dict(pt_slots=3), dict(pt_slots=4, replicas=66), dict(pt_slots=4, fixed_beta=True),
+                dict(pt_slots=4, beta=Fraction(0))):
+        kw = dict(replicas=64, sweeps=10, beta=Fraction(5))
+        kw.update(bad)
+        _expect(B.PBIT_EINVAL, prob, G.Params(**kw))
+        with pytest.raises(ValueError):
+            O.build_program(prob, G.Params(**kw))
+    _expect(B.PBIT_EINVAL, G.mkp(30, 3, G.rng_for(962, 1)), G.Params(replicas=64, sweeps=10, pt_slots=4))
+    for L in (2, 8, 64):
+        par = G.Params(replicas=128, sweeps=10, beta=Fraction(7), pt_slots=L)
+        info = B.pbit_plan(prob, par)
+        prog = O.build_program(prob, par)
+        assert info.lq_max == prog.lq_max and info.shift == prog.S
+        assert info.out_slot < info.out_bytes
