@@ -524,13 +524,23 @@ pbit_status make_plan(const pbit_problem *p, const pbit_params *par, Plan &P)
     P.hprof.resize(n);
     for (int i = 0; i < n; ++i) P.hprof[i] = (int32_t)h[i];
     if (P.variant == kQuad) {
-        // slabs of 32 rows (row stride n_pad + 16 bytes), slab stride 1 KB x (nb + 1)
+        // slabs of 32 rows (row stride n_pad + 16 bytes), slab stride 1 KB x (nb + 1).
+        // The diagonal 32 x 32 chunk of a slab is split in two: its strictly lower
+        // part (j < i, the in-block corrections with the current states) stays in
+        // place; the rest (j >= i, the block-start field) goes to the spare bytes,
+        // columns 0..15 of row r into the row's 16 padding bytes, columns 16..31
+        // into the slab's tail at 32 ls + 16 r.
         const int ls = P.n_pad + 16;
         const size_t slab = (size_t)1024 * (P.nb + 1);
         P.J.assign((size_t)P.nb * slab, 0);
         for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j)
-                P.J[(size_t)(i / 32) * slab + (size_t)(i % 32) * ls + j] = (int8_t)W[(size_t)i * n + j];
+            for (int j = 0; j < n; ++j) {
+                const int r = i % 32, cj = j % 32;
+                size_t at = (size_t)r * ls + j;
+                if (j / 32 == i / 32 && cj >= r)
+                    at = cj < 16 ? (size_t)r * ls + P.n_pad + cj : (size_t)32 * ls + (size_t)r * 16 + (cj - 16);
+                P.J[(size_t)(i / 32) * slab + at] = (int8_t)W[(size_t)i * n + j];
+            }
     }
     if (!make_theta(P.theta)) return fail(PBIT_ERANGE, "threshold table rounding undecidable");
 

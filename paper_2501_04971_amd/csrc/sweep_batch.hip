@@ -15,7 +15,7 @@ namespace pbit {
 template <int NB>
 __device__ __forceinline__ void batch_quad(const DevInstance &d, int rbase, unsigned char *smem)
 {
-    quad_run<NB, 4, false>(d, rbase, smem);
+    quad_run<NB, 4>(d, rbase, smem);
 }
 
 // A linear item is either a plain tile (4 waves visiting 256 replicas) or a

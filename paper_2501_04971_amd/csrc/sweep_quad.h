@@ -14,15 +14,14 @@
 // double-buffered: the next slab's pieces are loaded and stored to the free
 // buffer between the visits of the current block.  Each lane keeps its replica's state as
 // n_pad bytes in VGPRs.  Sites are visited in blocks of 32: at the start of a
-// block the 32 fields of the block are recomputed for all 64 replicas of the
-// wave with int8 MFMA (W[blk, :] . x); inside the block the earlier flips are
-// added with packed int8 dot products (W[i, blk] . dx).  The penalty is never
-// expanded into couplings: the constraint enters through the residual g.
-//
-// Visit pipeline: a flip of site s moves the field of site s+1 by the known
-// per-site constant c_{s+1} (Z_{s+1} = P + delta_s c_{s+1}), so while site s is
-// being decided both thresholds of site s+1 (s flips / s stays) are computed;
-// the dependent chain per visit is then one select, one compare and one xor.
+// block the 32 fields of the block are computed for all 64 replicas of the
+// wave with int8 MFMA, over every column except the block's own earlier sites
+// (W[i, j] with j in the block and j < i is left out: the host stores that
+// strictly lower part of the diagonal chunk apart, see diag_arow); the visit of
+// site i adds it with packed int8 dot products against the current state bytes
+// of the block (W[i, blk] . x), so that a decision feeds the next visit through
+// one state-byte update and one dot product.  The penalty is never expanded
+// into couplings: the constraint enters through the residual g.
 //
 // Register layout of the state: chunk c (sites 32c..32c+31) is 8 dwords per
 // lane.  Outside its own block a chunk is stored in the MFMA B-operand layout
@@ -51,9 +50,22 @@ __device__ __forceinline__ void fields_from_acc(const v16i &acc0, const v16i &ac
     }
 }
 
-// Block fields F[blk*32 + s] = sum_j W[blk*32+s, j] x_j for the 64 replicas of
-// the wave; slab holds rows blk*32..blk*32+31 of W.
+// MFMA A operand of a slab's diagonal chunk without its strictly lower part
+// (W[i, j], j >= i, both in the slab's block): the host stores columns 0..15 of
+// row r in the row's 16 padding bytes and columns 16..31 at 32 LS + 16 r, so
+// lane l (row l % 32, columns 16 (l / 32) ..) reads 16 bytes from there.
 template <int NB>
+__device__ __forceinline__ const int8_t *diag_arow(const int8_t *slab, int lane)
+{
+    constexpr int LS = NB * 32 + 16;
+    const int row = lane & 31;
+    return slab + (lane < 32 ? row * LS + NB * 32 : 32 * LS + row * 16);
+}
+
+// Block fields F[blk*32 + s] = sum_j W[blk*32+s, j] x_j for the 64 replicas of
+// the wave, except (FULL = false) the terms j = blk*32 + s' with s' < s (slab
+// holds rows blk*32..blk*32+31 of W).
+template <int NB, bool FULL = false>
 __device__ __forceinline__ void block_fields(const int8_t *slab, int blk, const uint32_t (&x)[NB][8],
                                              int32_t (&F)[32])
 {
@@ -66,11 +78,18 @@ __device__ __forceinline__ void block_fields(const int8_t *slab, int blk, const 
     for (int p = 0; p < NB; ++p) {
         int c = p + blk;
         c = c >= NB ? c - NB : c;
-        const v4i A = *reinterpret_cast<const v4i *>(arow + c * 32);
+        // p = 0 is the block's own chunk
+        const v4i A = *reinterpret_cast<const v4i *>(p == 0 ? diag_arow<NB>(slab, lane) : arow + c * 32);
         const v4i B0 = {(int)x[p][0], (int)x[p][1], (int)x[p][2], (int)x[p][3]};
         const v4i B1 = {(int)x[p][4], (int)x[p][5], (int)x[p][6], (int)x[p][7]};
         acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B0, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B1, acc1, 0, 0, 0);
+        if (FULL && p == 0) {
+            // the strictly lower part, kept in the chunk's own place
+            const v4i L = *reinterpret_cast<const v4i *>(arow + c * 32);
+            acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(L, B0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(L, B1, acc1, 0, 0, 0);
+        }
     }
     fields_from_acc(acc0, acc1, F);
 }
@@ -112,10 +131,8 @@ struct BlockVisit {
     const int64_t *rec;      // per-site records of the block
     const int8_t *wblk;      // LDS: W[blk*32 .., blk*32 ..]
     const int32_t *th;       // LDS threshold table
-    int32_t F[32];           // block fields at the block start
-    uint32_t dx[8];          // packed int8 flips of this block
+    int32_t F[32];           // block fields at the block start (without the lower in-block terms)
     uint32_t rnd[4];
-    uint32_t thA, thB, pend;
     int32_t g;
     int32_t Bt, ish, hclo, hchi;
     int64_t E;               // parallel tempering: D (L(x) - L(0)) carried as 2^u
@@ -153,56 +170,24 @@ __device__ __forceinline__ void stream_slab(BlockVisit &v)
     }
 }
 
-template <int s, int LS, int WPB>
-__device__ __forceinline__ void visit_site(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8])
-{
-    stream_slab<s, (LS - 16) / 32, WPB>(v);
-    // old states come from the block-start copy (site s changes only at its own
-    // visit), which keeps the record loads off the chain of decisions
-    const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
-    uint32_t nA = 0u, nB = 0u;
-    if constexpr (s < 31) {
-        const int64_t *nx = v.rec + 4 * (s + 1);
-        int32_t f = v.F[s + 1];
-        const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + (s + 1) * LS);
-#pragma unroll
-        for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
-        const uint32_t xo1 = (x0[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 1u;
-        const int64_t Z0 = nx[xo1] + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)nx[3], v.g) * v.k2;
-        const int64_t Z1 = Z0 + (xo ? -nx[2] : nx[2]);
-        nA = (uint32_t)v.th[theta_index(Z0, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
-        nB = (uint32_t)v.th[theta_index(Z1, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
-    }
-    if constexpr ((s & 3) == 0)
-        philox_block(v.cbase + (uint32_t)((v.blk * 32 + s) >> 2), v.kround, v.m2, v.inst, v.seed_lo,
-                     v.seed_hi, v.rnd);
-    const uint32_t u24 = v.rnd[s & 3] >> 8;
-    const int64_t meta = v.rec[4 * s + 3];
-    const uint32_t thr = (v.pend ? v.thB : v.thA) & (uint32_t)(meta >> 32);
-    const uint32_t xn = u24 < thr ? 1u : 0u;
-    const int32_t delta = (int32_t)xn - (int32_t)xo;
-    v.pend = xn ^ xo;
-    xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
-    v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
-    v.g += __mul24(delta, (int32_t)meta);
-    v.thA = nA;
-    v.thB = nB;
-}
-
-// One visit of site s without lookahead: its threshold is computed from the
-// current state right before the decision.  With parallel tempering the
-// replica's energy follows every flip: Z is -D times the energy change of
+// One visit of site s: its threshold index is computed from the current state
+// right before the decision.  The field adds W[s, s'] x_s' for the block's
+// earlier sites s' < s to the block-start field (the row's entries at s' >= s
+// are zero there, so whole state words can be used).  With parallel tempering
+// the replica's energy follows every flip: Z is -D times the energy change of
 // switching the site on, so a flip by delta changes D L by -delta Z.
 template <int s, int LS, int WPB, bool PT = false>
 __device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8])
 {
     stream_slab<s, (LS - 16) / 32, WPB>(v);
+    // old states come from the block-start copy (site s changes only at its own
+    // visit), which keeps the record loads off the chain of decisions
     const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
     const int64_t *cur = v.rec + 4 * s;
     int32_t f = v.F[s];
     const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + s * LS);
 #pragma unroll
-    for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
+    for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)xc[w], f, false);
     const int64_t meta = cur[3];
     const int64_t Z = cur[xo] + (int64_t)(f * 256) * v.sg2 - (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
     const uint32_t thr = (uint32_t)v.th[theta_index(Z, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf] &
@@ -214,7 +199,6 @@ __device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[
     const uint32_t xn = u24 < thr ? 1u : 0u;
     const int32_t delta = (int32_t)xn - (int32_t)xo;
     xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
-    v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
     v.g += __mul24(delta, (int32_t)meta);
     if constexpr (PT) v.E = delta > 0 ? v.E - Z : (delta < 0 ? v.E + Z : v.E);
 }
@@ -226,20 +210,17 @@ __device__ __forceinline__ void visit_site_direct(BlockVisit &v, uint32_t (&xc)[
 // Scheduling fence every PBIT_SCHED_WINDOW visits: keeps the compiler from
 // hoisting the loads of all 32 unrolled visits (which would cost registers and
 // therefore waves per SIMD) while leaving room to overlap neighbouring visits.
-template <int s>
+template <int s, int WIN = PBIT_SCHED_WINDOW>
 __device__ __forceinline__ void visit_fence()
 {
-    if constexpr ((s + 1) % PBIT_SCHED_WINDOW == 0) __builtin_amdgcn_sched_barrier(0);
+    if constexpr ((s + 1) % WIN == 0) __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int LS, int WPB, bool LA, bool PT, int... S>
+template <int LS, int WPB, bool PT, int... S>
 __device__ __forceinline__ void visit_block(BlockVisit &v, uint32_t (&xc)[8], std::integer_sequence<int, S...>)
 {
     const uint32_t x0[8] = {xc[0], xc[1], xc[2], xc[3], xc[4], xc[5], xc[6], xc[7]};
-    if constexpr (LA)
-        ((visit_site<S, LS, WPB>(v, xc, x0), visit_fence<S>()), ...);
-    else
-        ((visit_site_direct<S, LS, WPB, PT>(v, xc, x0), visit_fence<S>()), ...);
+    ((visit_site_direct<S, LS, WPB, PT>(v, xc, x0), visit_fence<S>()), ...);
 }
 
 // Replica exchange after sweep t (parallel tempering, chains of L lanes inside
@@ -293,7 +274,7 @@ __device__ __forceinline__ void pt_exchange(const DevInstance &d, int t, uint32_
 // One annealing run (T sweeps) of the replicas rbase + [0, 64 WPB) of instance
 // d, followed by the scoring of the final states.  The workgroup has WPB
 // waves; smem must hold quad_lds_bytes<NB>() bytes.
-template <int NB, int WPB, bool LA, bool PT = false>
+template <int NB, int WPB, bool PT = false>
 __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsigned char *smem)
 {
     constexpr int NP = NB * 32;        // padded spin count
@@ -366,18 +347,7 @@ __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsign
             v.rec = site + 4 * (blk * 32);
             v.wblk = slab + blk * 32;
             v.blk = blk;
-#pragma unroll
-            for (int w = 0; w < 8; ++w) v.dx[w] = 0u;
-            // thresholds of site 0 (nothing pending at a block start)
-            if constexpr (LA) {
-                const uint32_t xo0 = x[0][0] & 1u;
-                const int64_t Z = v.rec[xo0] + (int64_t)(v.F[0] * 256) * v.sg2 -
-                                  (int64_t)__mul24((int32_t)v.rec[3], v.g) * v.k2;
-                v.thA = (uint32_t)th[theta_index(Z, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) + kThetaHalf];
-                v.thB = v.thA;
-                v.pend = 0u;
-            }
-            visit_block<LS, WPB, LA, PT>(v, x[0], std::make_integer_sequence<int, 32>{});
+            visit_block<LS, WPB, PT>(v, x[0], std::make_integer_sequence<int, 32>{});
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             rotate_chunks<NB>(x);
@@ -397,7 +367,7 @@ __device__ __forceinline__ void quad_run(const DevInstance &d, int rbase, unsign
         const int8_t *slab = slabs + buf * SLAB;
         if (blk + 1 < NB) copy_slab<NB>(d.J, blk + 1, slabs + (buf ^ 1) * SLAB);
         int32_t F[32];
-        block_fields<NB>(slab, blk, x, F);
+        block_fields<NB, true>(slab, blk, x, F);
 #pragma unroll
         for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
         uint32_t bits = 0;

@@ -7,7 +7,7 @@ template <int NB, int WPB, bool PT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sweep_quad(const DevInstance d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    quad_run<NB, WPB, false, PT>(d, blockIdx.x * WPB * kWave, smem);
+    quad_run<NB, WPB, PT>(d, blockIdx.x * WPB * kWave, smem);
 }
 
 // PT: parallel tempering instead of annealing (d.pt > 0)

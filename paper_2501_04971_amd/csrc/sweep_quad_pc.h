@@ -33,35 +33,57 @@ constexpr size_t quad_pc_lds_bytes()
     return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 3 * (size_t)1024 * (NB + 1) + kRingBytes;
 }
 
-// Consumer visit of site s: thresholds on the field itself come from the ring.
+// Operands of one consumer visit, read from LDS a few visits ahead so that
+// the read latency stays off the chain of decisions: the threshold from the
+// ring, the record constant for the site's block-start state, the weight, and
+// the site's row of the strictly lower in-block part of W.
+struct VisitOps {
+    int64_t thr, K;
+    int32_t meta;
+    uint32_t w[8];
+};
+
 template <int s, int LS>
-__device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8],
-                                              const int64_t *ring)
+__device__ __forceinline__ void load_visit_ops(VisitOps &o, const BlockVisit &v, const uint32_t (&x0)[8],
+                                               const int64_t *ring)
 {
-    // site s changes only at its own visit, so its old state is read from the
-    // block-start copy: the record load below then waits on no earlier decision
-    const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
-    const int64_t *cur = v.rec + 4 * s;
-    const int64_t thr = ring[s * 64 + (threadIdx.x & 63)];
-    int32_t f = v.F[s];
-    const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + s * LS);
+    if constexpr (s < 32) {
+        // site s changes only at its own visit, so its old state is known from
+        // the block-start copy and the record is indexed by it
+        const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
+        const int64_t *cur = v.rec + 4 * s;
+        o.thr = ring[s * 64 + (threadIdx.x & 63)];
+        o.K = cur[xo];
+        o.meta = *reinterpret_cast<const int32_t *>(cur + 3);
+        const uint32_t *wrow = reinterpret_cast<const uint32_t *>(v.wblk + s * LS);
 #pragma unroll
-    for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)wrow[w], (int)v.dx[w], f, false);
-    const int64_t meta = cur[3];
-    // v.k2 holds -k2 here; the ring holds the threshold on the field itself
-    // (the record holds K0, K1 in its first two words: indexed by the old state)
-    const int64_t Z = cur[xo] + (int64_t)(f * 256) * v.sg2 + (int64_t)__mul24((int32_t)meta, v.g) * v.k2;
-    const uint32_t xn = Z >= thr ? 1u : 0u;
+        for (int w = 0; w < (s + 3) / 4; ++w) o.w[w] = wrow[w];
+    }
+}
+
+// Consumer visit of site s: the ring holds the threshold on the field itself.
+template <int s>
+__device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8],
+                                              const VisitOps &o)
+{
+    const uint32_t xo = (x0[s >> 2] >> (8 * (s & 3))) & 1u;
+    // block-start field plus the block's earlier sites at their current states
+    int32_t f = v.F[s];
+#pragma unroll
+    for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)o.w[w], (int)xc[w], f, false);
+    // v.k2 holds -k2 here
+    const int64_t Z = o.K + (int64_t)(f * 256) * v.sg2 + (int64_t)__mul24(o.meta, v.g) * v.k2;
+    const uint32_t xn = Z >= o.thr ? 1u : 0u;
     const int32_t delta = (int32_t)xn - (int32_t)xo;
     xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
-    v.dx[s >> 2] |= ((uint32_t)delta & 0xFFu) << (8 * (s & 3));
-    v.g += __mul24(delta, (int32_t)meta);
+    v.g += __mul24(delta, o.meta);
 }
 
 // Fields of the next block, accumulated on the matrix cores while the current
 // block is visited.  With the state rotated so that x[0] is the current block
 // b, the next block's field is W[b+1, :] . x = sum over chunks p = 1 .. NB-1 of
-// W[b+1, chunk (b+p)] . x[p] (unchanged by this block's visits) plus
+// W[b+1, chunk (b+p)] . x[p] (unchanged by this block's visits; p = 1 is the
+// next block's own chunk, without its strictly lower part) plus
 // W[b+1, chunk b] . x[0], added once the visits are done.  The partial products
 // are spread over the visits (one MFMA pair every STEP visits, operands loaded
 // at the block start), so their latency overlaps the visit chain instead of
@@ -70,6 +92,7 @@ template <int NB>
 struct NextFields {
     v16i acc0, acc1;
     const int8_t *arow;             // LDS: this lane's A-operand row of the next block's slab
+    const int8_t *adiag;            // LDS: its A operand of that slab's diagonal chunk (diag_arow)
     v4i a[NB > 1 ? NB - 1 : 1];     // A operands of chunks p = 1 .. NB-1, loaded at the block start
 
     // x[p] holds block (b + p) mod NB, whose columns of the next block's rows
@@ -80,7 +103,7 @@ struct NextFields {
         for (int p = 1; p < NB; ++p) {
             int c = b + p;
             c = c >= NB ? c - NB : c;
-            a[p - 1] = *reinterpret_cast<const v4i *>(arow + c * 32);
+            a[p - 1] = *reinterpret_cast<const v4i *>(p == 1 ? adiag : arow + c * 32);
         }
     }
 };
@@ -99,12 +122,28 @@ __device__ __forceinline__ void next_fields_step(NextFields<NB> &nf, const uint3
     }
 }
 
+// Scheduling window of the visiting wave (see visit_fence) and how many
+// visits ahead it reads its operands.
+#ifndef PBIT_PC_SCHED_WINDOW
+#define PBIT_PC_SCHED_WINDOW 4
+#endif
+#ifndef PBIT_PC_PREFETCH
+#define PBIT_PC_PREFETCH 4
+#endif
+
 template <int LS, int NB, int... S>
 __device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&x)[NB][8], NextFields<NB> &nf,
                                                const int64_t *ring, std::integer_sequence<int, S...>)
 {
+    constexpr int PF = PBIT_PC_PREFETCH;
     const uint32_t x0[8] = {x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], x[0][5], x[0][6], x[0][7]};
-    ((visit_site_pc<S, LS>(v, x[0], x0, ring), next_fields_step<S, NB>(nf, x), visit_fence<S>()), ...);
+    VisitOps ops[PF];
+    // the operands of the first PF visits, then each visit reads those of the
+    // visit PF places later into the slot it has just used
+    ((S < PF ? load_visit_ops<S < PF ? S : 32, LS>(ops[S % PF], v, x0, ring) : void()), ...);
+    ((visit_site_pc<S>(v, x[0], x0, ops[S % PF]), load_visit_ops<S + PF, LS>(ops[S % PF], v, x0, ring),
+      next_fields_step<S, NB>(nf, x), visit_fence<S, PBIT_PC_SCHED_WINDOW>()),
+     ...);
 }
 
 // Guess of the largest table position p with th[p] <= u from the inverse of
@@ -362,19 +401,19 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             v.rec = site + 4 * (blk * 32);
             v.wblk = slab + blk * 32;
             v.blk = blk;
-#pragma unroll
-            for (int w = 0; w < 8; ++w) v.dx[w] = 0u;
             NextFields<NB> nf;
             nf.acc0 = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
             nf.acc1 = nf.acc0;
             nf.arow = slabs + b1 * SLAB + (lane & 31) * LS + (lane >> 5) * 16;
+            nf.adiag = diag_arow<NB>(slabs + b1 * SLAB, lane);
             nf.load(blk);
             visit_block_pc<LS, NB>(v, x, nf, ring + buf * 32 * 64, std::make_integer_sequence<int, 32>{});
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             {
-                // this block's own chunk completes the next block's fields
-                const v4i A = *reinterpret_cast<const v4i *>(nf.arow + blk * 32);
+                // this block's chunk completes the next block's fields (with one
+                // block the next block is this one again: its diagonal chunk)
+                const v4i A = *reinterpret_cast<const v4i *>(NB == 1 ? nf.adiag : nf.arow + blk * 32);
                 const v4i B0 = {(int)x[0][0], (int)x[0][1], (int)x[0][2], (int)x[0][3]};
                 const v4i B1 = {(int)x[0][4], (int)x[0][5], (int)x[0][6], (int)x[0][7]};
                 nf.acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B0, nf.acc0, 0, 0, 0);
@@ -409,7 +448,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
         if (blk + 1 < NB) copy_slab<NB>(d.J, blk + 1, slabs + b1 * SLAB);
         if (wave == 0) {
             int32_t F[32];
-            block_fields<NB>(slab, blk, x, F);
+            block_fields<NB, true>(slab, blk, x, F);
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             uint32_t bits = 0;
