@@ -361,10 +361,15 @@ pbit_status pbit_destroy_batch(pbit_batch *batch);
  * A set encoder predicts lambda_0 for each constraint of an instance, to start
  * Algorithm 1 near the value its multipliers settle to (the paper starts from
  * lambda_0 = 0).  One set per (instance, constraint k), one element per
- * original variable i with features (bf16, 16 per element, four used)
- *   rho_i/(s_f n), n a_ki/b_k, n mean_k' a_k'i/b_k', h_i/s_f
- * where rho_i = h_i + sum_j W_ij, and a context of six values per set (bf16,
- * 16 stored): log(N_ext)/8, d, P/N_ext, beta_max/50, M/32, kind.
+ * original variable i with features (bf16, 16 per element, five used)
+ *   rho_i/(s_f n), n a_ki/b_k, n mean_k' a_k'i/b_k', h_i/s_f,
+ *   clamp(ln(e_ki / rho_bar_k), -8, 8)
+ * where rho_i = h_i + sum_j W_ij and e_ki = (h_i + sum_j W_ij / 2) / a_ki (+8
+ * for a_ki = 0, -8 for e_ki <= 0), and a context of nine values per set (bf16,
+ * 16 stored): log(N_ext)/8, d, P/N_ext, beta_max/50, M/32, kind, and of the
+ * greedy fill of constraint k alone (decreasing e_ki, ties by index, up to the
+ * first item that does not fit) that item's e / rho_bar_k (0 if all fit),
+ * b_k / sum_i a_ki and the items taken before it / n.
  * Network: phi = Linear(16,128)-ReLU-Linear(128,128)-ReLU per element, mean over
  * the set, head = Linear(144,128)-ReLU-Linear(128,1) on [pooled, context] -> t.
  * lambda_q,k = round_half_away(t * scale_k), scale_k = 256 rho_bar_k s_g / s_f,

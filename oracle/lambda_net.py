@@ -12,12 +12,17 @@ so that the loop can start near it.
 
 Set encoder, one set per (instance, constraint k), one element per original
 variable i:
-  features (F = 16, four used, the rest zero):
+  features (F = 16, five used, the rest zero):
     f0 = rho_i / (s_f n)         rho_i = h_i + sum_j W_ij  (profit row sum)
     f1 = n a_ki / b_k
     f2 = n mean_k' a_k'i / b_k'
     f3 = h_i / s_f
-  context (C = 6): log(N_ext)/8, d, P_n/N_ext, beta_max/50, M/32, kind
+    f4 = clamp(ln(e_ki / rho_bar_k), -8, 8), e_ki = (h_i + sum_j W_ij / 2) / a_ki
+         the item's profit per unit of weight k (+8 for a_ki = 0, -8 for e <= 0)
+  context (C = 9): log(N_ext)/8, d, P_n/N_ext, beta_max/50, M/32, kind, and
+    of the greedy fill of constraint k alone (items by decreasing e_ki, ties
+    by index, until the first that does not fit): e of that item / rho_bar_k
+    (0 if every item fits), b_k / sum_i a_ki, the items taken before it / n
   phi:  H1 = relu(X W1^T + b1), H2 = relu(H1 W2^T + b2)       (128 wide)
   pool: P = mean over the set's rows of H2
   head: z = [P, ctx, 0 pad] (144), G1 = relu(W3 z + b3), t = w4 . G1 + b4
@@ -49,7 +54,7 @@ import numpy as np
 from paper_2501_04971_amd.generators import KIND_QKP
 
 F_IN = 16
-N_CTX = 6
+N_CTX = 9
 Z_IN = 144
 HID = 128
 HUBER_DELTA = 1.0
@@ -124,6 +129,7 @@ def instance_features(prob, par, n_ext: int, pq: int, member: int = 0):
     half = (h + 0.5 * W.sum(axis=1)).sum()
     ctx = np.array([math.log(n_ext) / 8.0, d, (pq / 256.0) / n_ext, float(par.beta) / 50.0,
                     m / 32.0, 0.0 if prob.kind == KIND_QKP else 1.0])
+    hm = h + 0.5 * W.sum(axis=1)  # half-marginal profit of each item
     out = []
     for k in range(m):
         X = np.zeros((n, F_IN))
@@ -133,7 +139,25 @@ def instance_features(prob, par, n_ext: int, pq: int, member: int = 0):
         X[:, 3] = h / s_f
         asum = A[k].sum()
         rho_bar = half / (asum if asum > 0 else 1.0)
-        out.append(SetFeatures(X, ctx.copy(), 256.0 * rho_bar * s_g / s_f, member, k))
+        e = [math.inf if A[k, i] == 0 else float(hm[i]) / float(A[k, i]) for i in range(n)]
+        for i in range(n):
+            if e[i] == math.inf:
+                X[i, 4] = 8.0
+            elif e[i] <= 0.0 or rho_bar <= 0.0:
+                X[i, 4] = -8.0
+            else:
+                X[i, 4] = min(8.0, max(-8.0, math.log(e[i] / rho_bar)))
+        # greedy fill of constraint k alone
+        order = sorted(range(n), key=lambda i: (-e[i], i))
+        used, taken, e_break = 0.0, 0, 0.0
+        for i in order:
+            if used + A[k, i] > b[k]:
+                e_break = e[i]
+                break
+            used += A[k, i]
+            taken += 1
+        greedy = [e_break / rho_bar if rho_bar > 0 else 0.0, b[k] / (asum if asum > 0 else 1.0), taken / n]
+        out.append(SetFeatures(X, np.concatenate([ctx, greedy]), 256.0 * rho_bar * s_g / s_f, member, k))
     return out
 
 

@@ -1578,6 +1578,8 @@ pbit_status pbit_net_pack(const pbit_problem *probs, const pbit_params *params, 
                               ((double)params[i].beta_num / params[i].beta_den) / 50.0, m / 32.0,
                               p.kind == PBIT_QKP ? 0.0 : 1.0};
         const int span = ((n + 31) / 32) * 32;
+        std::vector<double> eff(n);
+        std::vector<int> order(n);
         for (int k = 0; k < m; ++k, ++s) {
             set_rows[s] = r;
             set_n[s] = n;
@@ -1593,8 +1595,36 @@ pbit_status pbit_net_pack(const pbit_problem *probs, const pbit_params *params, 
                 row[2] = to_bf16(n * mean_ratio[a]);
                 row[3] = to_bf16(h[a] / s_f);
             }
-            for (int c = 0; c < 6; ++c) ctx[(size_t)s * kNetCtx + c] = to_bf16(c6[c]);
             const double rho_bar = half / (asum > 0 ? asum : 1.0);
+            // profit per unit of weight k (half-marginal profit), relative to rho_bar
+            for (int a = 0; a < n; ++a) {
+                const double ak = p.weight[(size_t)k * n + a];
+                eff[a] = ak == 0 ? HUGE_VAL : (h[a] + 0.5 * wsum[a]) / ak;
+                double f4;
+                if (eff[a] == HUGE_VAL) f4 = 8.0;
+                else if (eff[a] <= 0.0 || rho_bar <= 0.0) f4 = -8.0;
+                else f4 = std::min(8.0, std::max(-8.0, std::log(eff[a] / rho_bar)));
+                x[(size_t)(r + a) * kNetF + 4] = to_bf16(f4);
+            }
+            // greedy fill of constraint k alone: decreasing efficiency, ties by index
+            for (int a = 0; a < n; ++a) order[a] = a;
+            std::sort(order.begin(), order.end(),
+                      [&eff](int u, int v) { return eff[u] != eff[v] ? eff[u] > eff[v] : u < v; });
+            double used = 0.0, e_break = 0.0;
+            int taken = 0;
+            for (int a : order) {
+                const double ak = p.weight[(size_t)k * n + a];
+                if (used + ak > (double)p.capacity[k]) {
+                    e_break = eff[a];
+                    break;
+                }
+                used += ak;
+                ++taken;
+            }
+            const double c9[9] = {c6[0], c6[1], c6[2], c6[3], c6[4], c6[5],
+                                  rho_bar > 0 ? e_break / rho_bar : 0.0,
+                                  (double)p.capacity[k] / (asum > 0 ? asum : 1.0), (double)taken / n};
+            for (int c = 0; c < 9; ++c) ctx[(size_t)s * kNetCtx + c] = to_bf16(c9[c]);
             scale[s] = 256.0 * rho_bar * s_g / s_f;
             r += span;
         }

@@ -4,8 +4,8 @@
 
 namespace pbit {
 
-constexpr int kNetF = 16;    // input features per element (four used)
-constexpr int kNetCtx = 16;  // context values per set as stored (six used)
+constexpr int kNetF = 16;    // input features per element (five used)
+constexpr int kNetCtx = 16;  // context values per set as stored (nine used)
 constexpr int kNetH = 128;   // hidden width
 constexpr int kNetZ = 144;   // head input: pooled (128) + context (16)
 

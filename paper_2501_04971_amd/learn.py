@@ -190,7 +190,7 @@ class Trainer:
         return lam.view(count, 32)
 
 
-DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "lambda0_qkp.npz")
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "lambda0.npz")
 
 
 def predict_lambda0(probs, pars, weights: str = DEFAULT_WEIGHTS):
@@ -235,11 +235,14 @@ def cmd_train(args):
     def make(sel):
         pk = B.pbit_net_pack([ms[i][0] for i in sel], [ms[i][1] for i in sel])
         y = np.zeros(pk["sets"], np.float32)
+        qkp = np.zeros(pk["sets"], bool)
         for s in range(pk["sets"]):
             mem, k = divmod(int(pk["dest"][s]), 32)
             y[s] = lstar[sel[mem], k] / pk["scale"][s]
+            qkp[s] = ms[sel[mem]][0].kind == G.KIND_QKP
         d = Trainer.upload(pk)
         d["y"] = torch.from_numpy(y).cuda()
+        d["qkp"] = qkp
         return d
 
     batches = [make(tr[i:i + mb]) for i in range(0, len(tr), mb)]
@@ -260,8 +263,10 @@ def cmd_train(args):
         if ep % max(1, args.epochs // 20) == 0 or ep == args.epochs - 1:
             print(f"epoch {ep}: train {tot / len(batches):.5f} val {vl:.5f}", flush=True)
     ytr = np.concatenate([b["y"].cpu().numpy() for b in batches])
+    qtr = np.concatenate([b["qkp"] for b in batches])
+    med = {f"y_median_{k}": float(np.median(ytr[sel])) for k, sel in (("qkp", qtr), ("mkp", ~qtr)) if sel.any()}
     np.savez(args.out, weights=T.w.cpu().numpy(), history=np.array(hist),
-             train_index=idx[tr], val_index=idx[val], y_median=np.median(ytr))
+             train_index=idx[tr], val_index=idx[val], y_median=np.median(ytr), **med)
     print(json.dumps({"out": args.out, "train": len(tr), "val": len(val), "final_val_loss": hist[-1][1]}),
           flush=True)
 
@@ -283,16 +288,91 @@ def compare(plain, other, K: int, R: int):
     so_fb = np.where(fb, np.where(so > 0, so, K * R) + sp, so)
     both = ok & (sp > 0) & (so_fb > 0)
     ratio = sp[both] / so_fb[both]
+    lo, hi = bootstrap_geomean_ci(ratio)
     return {
-        "rounds": K, "plain_feasible": int(ok.sum()), "reached_target": int((so > 0)[ok].sum()),
+        "rounds": K, "plain_feasible": int(ok.sum()), "other_feasible": int(oh[-1].sum()),
+        "reached_target": int((so > 0)[ok].sum()),
         "fallbacks": int(fb[ok].sum()),
         "median_samples_plain": float(np.median(sp[both])) if both.any() else None,
         "median_samples_other": float(np.median(so_fb[both])) if both.any() else None,
         "geomean_ratio_plain_over_other": float(np.exp(np.mean(np.log(ratio)))) if both.any() else None,
+        "geomean_ratio_ci95": [lo, hi],
         "median_ratio_plain_over_other": float(np.median(ratio)) if both.any() else None,
         "fraction_fewer_samples": float((so_fb[both] < sp[both]).mean()) if both.any() else None,
         "final_best_ratio_mean": float(np.mean(np.where(oh[-1], ob[-1], 0)[ok] / np.maximum(pb[-1][ok], 1))),
     }
+
+
+def bootstrap_geomean_ci(ratio, reps: int = 2000, seed: int = 0):
+    """95 % percentile bootstrap interval of the geometric mean of ratios
+    (instances resampled with replacement)."""
+    if len(ratio) == 0:
+        return None, None
+    rng = np.random.default_rng(seed)
+    logs = np.log(np.asarray(ratio, dtype=np.float64))
+    means = logs[rng.integers(0, len(logs), size=(reps, len(logs)))].mean(axis=1)
+    return float(np.exp(np.percentile(means, 2.5))), float(np.exp(np.percentile(means, 97.5)))
+
+
+def scale_only_lambda0(probs, pars, weights: str = DEFAULT_WEIGHTS) -> np.ndarray:
+    """Host int32 [count][32] scale-only start for the given instances: the
+    analytic scale times the training targets' median t of the member's kind."""
+    z = np.load(weights)
+    pk = B.pbit_net_pack(probs, pars)
+    lam = np.zeros((len(probs), 32), dtype=np.int32)
+    for kind, is_q in (("qkp", True), ("mkp", False)):
+        c = float(z[f"y_median_{kind}"]) if f"y_median_{kind}" in z.files else float(z["y_median"])
+        part = scale_only_start(pk, len(probs), c)
+        for i, p in enumerate(probs):
+            if (p.kind == G.KIND_QKP) == is_q:
+                lam[i] = part[i]
+    return lam
+
+
+def scale_only_start(pk, count: int, c: float) -> np.ndarray:
+    """lambda_0 = round(c * scale_k) for every set: the analytic scale of the
+    prediction times one constant (the training targets' median t)."""
+    lam = np.zeros((count, 32), dtype=np.int32)
+    for s in range(pk["sets"]):
+        v = c * pk["scale"][s]
+        lam.reshape(-1)[pk["dest"][s]] = int(np.floor(abs(v) + 0.5)) * (1 if v >= 0 else -1)
+    return lam
+
+
+def evaluate(weights: str, indices, rounds_qkp: int, rounds_mkp: int, mkp_eta=None, log=print):
+    """Plain, learned and scale-only starts on the given instances, QKP and MKP
+    members run as separate batches; samples-to-target per kind (MKP members
+    at step mkp_eta instead of Table 1's when given)."""
+    z = np.load(weights)
+    T = Trainer(weights=z["weights"])
+    out = {"instances": len(indices)}
+    for kind, K in (("qkp", rounds_qkp), ("mkp", rounds_mkp)):
+        # the scale-only start takes the training targets' median t of its own kind
+        c = float(z[f"y_median_{kind}"]) if f"y_median_{kind}" in z.files else float(z["y_median"])
+        idx = [i for i in indices if (learn_instance(i)[0].kind == G.KIND_QKP) == (kind == "qkp")]
+        if not idx or K <= 0:
+            continue
+        ms = [learn_instance(i) for i in idx]
+        if kind == "mkp" and mkp_eta is not None:
+            ms = [(p, dataclasses.replace(q, eta=Fraction(mkp_eta))) for p, q in ms]
+        probs, pars = [p for p, _ in ms], [q for _, q in ms]
+        pk = B.pbit_net_pack(probs, pars)
+        d = Trainer.upload(pk)
+        lam0 = T.predict_lambda(d, len(ms)).cpu().numpy().reshape(len(ms), 32)
+        lam_c = scale_only_start(pk, len(ms), c)
+        log(f"eval {kind}: {len(ms)} instances, {K} rounds per start")
+        plain = run_loop(probs, pars, K, log=log)
+        learned = run_loop(probs, pars, K, lambda0=lam0, log=log)
+        const = run_loop(probs, pars, K, lambda0=lam_c, log=log)
+        R = pars[0].replicas
+        res = {"instances": len(ms), "replicas": R, "rounds": K, "median_t": c, "eta": str(pars[0].eta),
+               "by_rounds": {}}
+        for k in sorted({K // 4, K // 2, K}):
+            res["by_rounds"][str(k)] = {"learned": compare(plain, learned, k, R),
+                                        "scale_only": compare(plain, const, k, R),
+                                        "learned_vs_scale_only": compare(const, learned, k, R)}
+        out[kind] = res
+    return out
 
 
 def cmd_eval(args):
@@ -334,6 +414,15 @@ def cmd_eval(args):
     return res
 
 
+def cmd_heldout(args):
+    res = evaluate(args.weights, list(range(args.first, args.first + args.count)), args.rounds_qkp,
+                   args.rounds_mkp, mkp_eta=args.mkp_eta)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f)
+    print(json.dumps(res), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -358,8 +447,16 @@ def main(argv=None):
     e.add_argument("--count", type=int, default=256)
     e.add_argument("--rounds", type=int, default=100)
     e.add_argument("--out", default="")
+    h = sub.add_parser("heldout", help="plain / learned / scale-only on held-out QKP and MKP instances")
+    h.add_argument("--weights", required=True)
+    h.add_argument("--first", type=int, default=EVAL_SEED_BASE)
+    h.add_argument("--count", type=int, default=1000)
+    h.add_argument("--rounds-qkp", type=int, default=400)
+    h.add_argument("--rounds-mkp", type=int, default=600)
+    h.add_argument("--mkp-eta", default=None, help="MKP step (a fraction, e.g. 1/2) instead of Table 1's")
+    h.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    {"gen": cmd_gen, "train": cmd_train, "eval": cmd_eval}[args.cmd](args)
+    {"gen": cmd_gen, "train": cmd_train, "eval": cmd_eval, "heldout": cmd_heldout}[args.cmd](args)
     return 0
 
 

@@ -40,7 +40,7 @@ def test_pack_matches_oracle_features(lib):
             assert pk["set_rows"][s + 1] - r0 == (prob.n + 31) // 32 * 32
             assert (pk["x"][r0:r0 + n] == bits(f.X)).all(), f"set {s}: features differ"
             assert not pk["x"][r0 + n:pk["set_rows"][s + 1]].any()
-            assert (pk["ctx"][s, :6] == bits(f.ctx)).all() and not pk["ctx"][s, 6:].any()
+            assert (pk["ctx"][s, :9] == bits(f.ctx)).all() and not pk["ctx"][s, 9:].any()
             assert pk["scale"][s] == f.scale
             assert pk["dest"][s] == i * 32 + f.k
             s += 1

@@ -123,11 +123,16 @@ def test_features_of_a_tiny_instance():
     assert np.allclose(X[:, 1], [2 * 1 / 2, 2 * 3 / 2])
     assert np.allclose(X[:, 2], X[:, 1])
     assert np.allclose(X[:, 3], [4 / 6, 1.0])
-    assert not X[:, 4:].any()
+    # efficiencies e = (h + W/2) / a: 5 / 1 and 7 / 3, relative to rho_bar = 3
+    assert np.allclose(X[:, 4], [np.log(5 / 3), np.log(7 / 9)])
+    assert not X[:, 5:].any()
     # rho_bar = (4 + 1 + 6 + 1) / (1 + 3) = 3; scale = 256 * 3 * s_g / s_f, s_g = 3
     assert abs(fs[0].scale - 256 * 3 * 3 / 6) < 1e-12
     assert prog.n_ext == 4  # two slack bits for b = 2
-    assert np.allclose(fs[0].ctx, [np.log(4) / 8, 1.0, prog.pq / 256 / 4, 5 / 50, 1 / 32, 0.0])
+    # greedy fill of b = 2: item 0 (weight 1) fits, item 1 (weight 3) is the
+    # first that does not: e = 7/3 -> 7/9; b / sum a = 2/4; one item of two taken
+    assert np.allclose(fs[0].ctx, [np.log(4) / 8, 1.0, prog.pq / 256 / 4, 5 / 50, 1 / 32, 0.0,
+                                   7 / 9, 0.5, 0.5])
 
 
 def test_to_lambda_q_rounds_half_away():
