@@ -25,8 +25,9 @@ __device__ __forceinline__ void batch_quad(const DevInstance &d, int rbase, unsi
 template <int M, bool WIDE>
 __device__ __forceinline__ void batch_linear(const DevInstance &d, int rbase, bool split, unsigned char *smem)
 {
-    if (split) linear_run_pc<M, WIDE>(d, rbase, smem);
-    else linear_run_lds<M, WIDE>(d, rbase, smem);
+    // operands read at the visit: this kernel's registers are full (see lin_read_ahead)
+    if (split) linear_run_pc<M, WIDE, false>(d, rbase, smem);
+    else linear_run_lds<M, WIDE, false>(d, rbase, smem);
 }
 
 #define PBIT_BQ(nb)                                                                         \

@@ -251,12 +251,42 @@ __device__ __forceinline__ int64_t residual_dot(const int32_t *a, const int32_t 
     return t;
 }
 
+// Operands of one original-item visit (the item's weights and the record
+// constant for its old state), read from LDS one visit ahead so that the read
+// latency stays off the chain of decisions.  This pays where one wave per
+// SIMD visits (the split form); two sets cost 2 (M + 2) registers, which the
+// bodies with more than 16 constraints cannot spare: those read at the visit,
+// and so do the bodies inside the batch kernel (whose registers are already
+// full with the widest body) and the plain body, whose four waves per
+// workgroup hide the latency for one another.
+template <int M>
+constexpr bool lin_read_ahead()
+{
+    return M <= 16;
+}
+
+template <int M>
+struct LinOps {
+    int32_t a[M];
+    int64_t K;
+};
+
+template <int M>
+__device__ __forceinline__ void load_lin_ops(LinOps<M> &o, const int32_t *ac, const int64_t *kr, int i,
+                                             uint32_t xo)
+{
+    const int32_t *a = ac + i * M;
+#pragma unroll
+    for (int k = 0; k < M; ++k) o.a[k] = a[k];
+    o.K = kr[2 * i + xo];
+}
+
 // The same annealing run with every per-site constant resident in LDS and each
 // visit computed directly from the current residuals: field, threshold index,
 // table lookup, decision, O(M) residual update.  No scalar-memory loads in the
 // sweep, so waits on LDS never wait on scalar loads.  The host uses it whenever
 // linear_lds_resident_bytes fits a workgroup.
-template <int M, bool WIDE>
+template <int M, bool WIDE, bool AHEAD = false>
 __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, unsigned char *smem)
 {
     const int words = d.words, owords = d.owords;
@@ -305,14 +335,21 @@ __device__ __forceinline__ void linear_run_lds(const DevInstance &d, int rbase, 
             uint32_t xw = xw0;
             const int rem = n - blk * 32;  // original items in this word (the rest are not visited here)
             uint32_t rnd[4];
+            LinOps<AHEAD ? M : 1> op[2];
+            if constexpr (AHEAD) load_lin_ops<M>(op[0], ac, kr, blk * 32, xw0 & 1u);
 #pragma unroll
             for (int s = 0; s < 32; ++s) {
                 const int i = blk * 32 + s;
+                if constexpr (AHEAD) {
+                    // the next visit's operands first (site blk*32 + 31 < owords*32: in bounds)
+                    if (s + 1 < 32) load_lin_ops<M>(op[(s + 1) & 1], ac, kr, i + 1, (xw0 >> (s + 1)) & 1u);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
                 if ((s & 3) == 0)
                     philox_block(cbase + (uint32_t)(i >> 2), kround, m2, d.inst_id, d.seed_lo, d.seed_hi, rnd);
                 const uint32_t xo = (xw0 >> s) & 1u;
-                const int32_t *a = ac + i * M;
-                const int64_t K = kr[2 * i + xo];
+                const int32_t *a = AHEAD ? op[s & 1].a : ac + i * M;
+                const int64_t K = AHEAD ? op[s & 1].K : kr[2 * i + xo];
                 const int64_t dd = residual_dot<M, WIDE>(a, g);
                 const int64_t Z = WIDE ? K + dd * (int64_t)negk2 : K + (int64_t)(int32_t)dd * negk2;
                 const uint32_t thr = (uint32_t)th[theta_index(Z, Bt, ish, irnd, hclo, hchi) + kThetaHalf] &

@@ -21,7 +21,7 @@ inline size_t linear_pc_lds_bytes(int words, int owords, int m)
            (size_t)owords * 32 * m * 4 + (size_t)words * kWave * 4;
 }
 
-template <int M, bool WIDE>
+template <int M, bool WIDE, bool AHEAD = lin_read_ahead<M>()>
 __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, unsigned char *smem)
 {
     const int words = d.words, owords = d.owords;
@@ -85,13 +85,27 @@ __device__ __forceinline__ void linear_run_pc(const DevInstance &d, int rbase, u
                 const uint32_t xw0 = xl[w * kWave + lane];
                 uint32_t xw = xw0;
                 const int rem = n - base;
+                // operands read one visit ahead (sites up to base + 31 < owords*32: in bounds)
+                LinOps<AHEAD ? M : 1> op[2];
+                int64_t ztn[2];
+                if constexpr (AHEAD) {
+                    load_lin_ops<M>(op[0], ac, kr, base, xw0 & 1u);
+                    ztn[0] = rg[lane];
+                }
 #pragma unroll
                 for (int s = 0; s < 32; ++s) {
                     const int i = base + s;
-                    const int64_t zt = rg[s * 64 + lane];
+                    if constexpr (AHEAD) {
+                        if (s + 1 < 32) {
+                            load_lin_ops<M>(op[(s + 1) & 1], ac, kr, i + 1, (xw0 >> (s + 1)) & 1u);
+                            ztn[(s + 1) & 1] = rg[(s + 1) * 64 + lane];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                     const uint32_t xo = (xw0 >> s) & 1u;
-                    const int32_t *a = ac + i * M;
-                    const int64_t K = kr[2 * i + xo];
+                    const int64_t zt = AHEAD ? ztn[s & 1] : rg[s * 64 + lane];
+                    const int32_t *a = AHEAD ? op[s & 1].a : ac + i * M;
+                    const int64_t K = AHEAD ? op[s & 1].K : kr[2 * i + xo];
                     const int64_t dd = residual_dot<M, WIDE>(a, g);
                     const int64_t Z = WIDE ? K + dd * (int64_t)negk2 : K + (int64_t)(int32_t)dd * negk2;
                     // sites past the original items belong to the slack loop: never flip here
