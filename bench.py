@@ -163,7 +163,7 @@ def cpu_baseline(members, seconds_target: float = 15.0):
                      "threads_rule": f"min(usable CPUs, {HOST_CPU_SHARE})"}}
 
 
-def learned_start_summary(count: int = 200, rounds: int = 300):
+def learned_start_summary(count: int = 400, rounds: int = 300):
     """Samples to reach the plain loop's best feasible profit (less 0.1 %) on
     held-out QKP N=300 d=1 instances (the throughput workload's generator,
     Table 1's QKP settings): plain start (lambda_0 = 0) against the shipped set

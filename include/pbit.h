@@ -380,7 +380,15 @@ pbit_status pbit_destroy_batch(pbit_batch *batch);
  * for the per-element layers).  All device buffers are caller-owned. */
 int32_t pbit_net_param_count(void);
 
-/* Device workspace for the activations of one forward/backward pair. */
+/* Device workspace for the activations of one forward/backward pair.  Its
+ * layout (each part at the next 256-byte boundary, in this order) lets a
+ * caller inspect them after pbit_net_forward / pbit_net_backward:
+ *   H1 bf16 [rows][128], H2 bf16 [rows][128]   per-element activations
+ *   Z  bf16 [sets][144]                        pooled mean of H2 over the set's
+ *                                              n rows, then the 16 context values
+ *   G1 bf16 [sets][128]                        head hidden layer
+ *   dP fp32 [sets][128]                        loss gradient w.r.t. the pooled mean
+ *   then per-group partial gradients (internal). */
 size_t pbit_net_workspace_bytes(int32_t sets, int32_t rows);
 
 /* Host: packs the sets of count instances.  Always writes *sets and *rows (a

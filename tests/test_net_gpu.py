@@ -4,8 +4,12 @@ The kernels keep bf16 weights and activations and accumulate in fp32; the
 oracle rounds at the same points and accumulates exactly.  The two differ by
 fp32 summation error (relative ~1e-6) and, where that error straddles a bf16
 rounding boundary, by one bf16 ulp (2^-8 relative) in single activations.
-Bound used: per parameter group, max |gpu - ref| <= 2e-2 max |ref| and the
-relative L2 error <= 1e-2; the outputs t within 1e-2 (1 + |t|)."""
+End to end against the oracle (which rounds its own activations, so single
+flips propagate): per parameter group, max |gpu - ref| <= 2e-2 max |ref| and
+the relative L2 error <= 1e-2; the outputs t within 1e-2 (1 + |t|).  Layer by
+layer from the device's stored activations, every element is held to its own
+rounding bound (tests/net_bounds.py), at most a few 1e-4 of its group's
+largest entry."""
 from fractions import Fraction
 
 import numpy as np
@@ -111,6 +115,59 @@ def test_forward_and_backward_match_oracle(need_gpu, packed, seed):
     gp, rp = N.unflatten(grad.astype(np.float64)), N.unflatten(gref)
     for name, _ in N.LAYOUT:
         check_close(gp[name], rp[name], name)
+
+
+def _ws_parts(ws, S, R):
+    """The activations in the workspace (layout of pbit_net_workspace_bytes)."""
+    def up(o):
+        return (o + 255) // 256 * 256
+    raw = ws.cpu().numpy()
+    o_h2 = up(R * N.HID * 2)
+    o_z = o_h2 + up(R * N.HID * 2)
+    o_g1 = o_z + up(S * N.Z_IN * 2)
+    o_dp = o_g1 + up(S * N.HID * 2)
+
+    def bf(off, shape):
+        n = int(np.prod(shape))
+        return bf_bits_to_f64(raw[off:off + 2 * n].view(np.uint16)).reshape(shape)
+    dP = raw[o_dp:o_dp + 4 * S * N.HID].view(np.float32).astype(np.float64).reshape(S, N.HID)
+    return {"H1": bf(0, (R, N.HID)), "H2": bf(o_h2, (R, N.HID)), "Z": bf(o_z, (S, N.Z_IN)),
+            "G1": bf(o_g1, (S, N.HID)), "dP": dP}
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_every_element_within_its_rounding_bound(need_gpu, packed, seed):
+    """Layer by layer from the device's own stored activations, every stored
+    activation lies in the bf16 rounding interval of its fp32 sum and t, the
+    loss, dP and every gradient entry within the fp32 accumulation bound of
+    its exact value (tests/net_bounds.py): a per-element check, where the test
+    above bounds whole parameter groups."""
+    import torch
+    import net_bounds as NB
+    ms, pk = packed
+    S, R = pk["sets"], pk["rows"]
+    say(f"[net bounds] sets={S} rows={R} seed={seed}")
+    w = N.init_params(seed)
+    y32 = (np.random.default_rng(seed).normal(size=S) * 1.5).astype(np.float32)
+    wt = dev(w.astype(np.float32))
+    wb = torch.empty(wt.numel(), dtype=torch.int16, device="cuda")
+    B.pbit_net_cast(wt, wb)
+    x, ctx = dev(pk["x"].view(np.int16)), dev(pk["ctx"].view(np.int16))
+    sr, sn = dev(pk["set_rows"]), dev(pk["set_n"])
+    ws = torch.empty(B.pbit_net_workspace_bytes(S, R), dtype=torch.uint8, device="cuda")
+    t = torch.empty(S, dtype=torch.float32, device="cuda")
+    B.pbit_net_forward(wb, x, ctx, sr, sn, S, R, ws, t)
+    grad = torch.empty(wt.numel(), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    B.pbit_net_backward(wb, x, sr, sn, S, R, t, dev(y32), ws, grad, loss)
+    torch.cuda.synchronize()
+    d = _ws_parts(ws, S, R)
+    d.update({"X": bf_bits_to_f64(pk["x"]), "ctx": bf_bits_to_f64(pk["ctx"]),
+              "t": t.cpu().numpy().astype(np.float64), "loss": float(loss.cpu()[0]),
+              "grad": grad.cpu().numpy().astype(np.float64)})
+    wq = bf_bits_to_f64(wb.cpu().numpy().view(np.uint16))
+    worst = NB.check(pk, wq, y32, d)
+    say(f"[net bounds] largest bound / group max = {worst:.2e}")
 
 
 def test_backward_is_deterministic(need_gpu, packed):
