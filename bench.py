@@ -26,6 +26,13 @@ import os
 import sys
 import time
 
+# The concurrent-instances leg runs four instances on four streams besides the
+# default one; with four hardware queues per process (HIP's default) two of
+# them can land on one queue and run one after the other.  Eight queues, set
+# before the HIP runtime starts, give every stream its own.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 # Algorithmic integer ALU work of one spin update outside the field dot product
 # (which the int8 matrix cores do for the quadratic kernel): a quarter of a
 # Philox4x32-10 block (10 rounds x 8 32-bit ops / 4), the field combination
@@ -328,7 +335,7 @@ def main() -> int:
         fits = info.variant == 0 or linear_split_lds(info, prob.n) <= 160 * 1024
         split = groups <= torch.cuda.get_device_properties(0).multi_processor_count and fits
         nb = info.n_pad // 32
-        producers = 6 if info.variant == 0 and nb <= 4 else 3  # the library's default for the split form
+        producers = 6 if info.variant == 0 else 3  # the library's default for the split form
         waves = (8 if producers == 6 else 4) * groups if split else groups
         best = runner.best_feasible()
         wide = "true" if info.variant == 2 else "false"

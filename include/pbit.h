@@ -255,8 +255,7 @@ pbit_status pbit_instance_info(const pbit_instance *inst, pbit_plan_info *out);
  * draws and thresholds (and, for the quadratic kernel, its J slabs) (1), for
  * the quadratic kernel the same with six such waves, two per SIMD (2), plain
  * workgroups (0), or the split form whenever the replicas leave CUs idle and
- * it fits LDS (-1, the default; quadratic: six producers up to 128 padded
- * spins, three above).  Every layout gives bit-identical results;
+ * it fits LDS (-1, the default; quadratic: six producers).  Every layout gives bit-identical results;
  * only the speed differs.  Host only, takes effect at the next
  * pbit_sample_round.  PBIT_ERANGE if lds_resident = 1 or split = 1 does not
  * fit the 160 KB of LDS. */
