@@ -196,6 +196,36 @@ def learned_start_summary(count: int = 400, rounds: int = 300):
             "learned_vs_scale_only": L.compare(const, learned, rounds, R)}
 
 
+def tempering_leg(workload: int, slots: int, rounds: int):
+    """The same instance with parallel tempering as the sampler (chains of
+    `slots` replicas on a linear beta ladder, exchanges after every sweep; the
+    plain kernel, every lane at its own temperature): spin updates/s over
+    `rounds` rounds, exchanges included, HIP events on the launch stream."""
+    import dataclasses
+    import torch
+    from paper_2501_04971_amd import binding as B
+    from paper_2501_04971_amd import generators as G
+    prob, par, _ = G.workload(workload, 0)
+    par = dataclasses.replace(par, pt_slots=slots)
+    inst = B.Instance(prob, par)
+    inst.sample_round()
+    inst.update_lambda()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(rounds):
+        inst.sample_round()
+        inst.update_lambda()
+    b.record(s)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / rounds
+    updates = par.replicas * inst.info.n_ext * par.sweeps
+    inst.close()
+    return {"slots": slots, "chains": par.replicas // slots, "rounds": rounds, "ms_per_round": ms,
+            "spin_updates_per_s": updates / (ms / 1e3)}
+
+
 def concurrent_instances(workload: int, count: int, rounds: int):
     """count instances of the workload (indices 0 .. count-1), each on a stream
     of its own, all rounds queued before any is waited on: the chip-level rate
@@ -239,6 +269,8 @@ def main() -> int:
     ap.add_argument("--instance", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the samples-to-target comparison")
+    ap.add_argument("--pt-slots", type=int, default=32,
+                    help="also time the QKP workload with parallel tempering, chains of this many replicas (0: skip)")
     ap.add_argument("--concurrent", type=int, default=4,
                     help="also time this many instances of the workload side by side (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -385,6 +417,8 @@ def main() -> int:
     }
     if args.concurrent > 1 and not batch:
         out["concurrent"] = concurrent_instances(args.workload, args.concurrent, max(2, min(args.steps, 5)))
+    if args.pt_slots > 0 and args.workload in (0, 2):
+        out["parallel_tempering"] = tempering_leg(args.workload, args.pt_slots, max(2, min(args.steps, 3)))
     if not args.no_learned and args.workload == 2:
         out["samples_to_target"] = learned_start_summary()
     if not args.no_cpu_baseline:

@@ -1109,13 +1109,12 @@ pbit_status pbit_sample_round(pbit_instance *inst, pbit_stream stream)
     hipError_t e;
     switch (inst->plan.variant) {
         case kQuad: {
-            // parallel tempering runs in the plain kernel (every lane its own temperature)
-            const bool pc = d.pt == 0 &&
-                            (inst->split >= 1 || (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus));
+            const bool pc = inst->split >= 1 || (inst->split < 0 && (d.R + kWave - 1) / kWave <= inst->cus);
             // six producers (two waves per SIMD) by default: with the visiting
             // wave reading its operands ahead the producers bound the round
-            // (measured: 10 blocks 114.8 -> 90.7 ms, 4 blocks 8.7 -> 6.5 ms)
-            const int producers = inst->split == 1 ? 3 : 6;
+            // (measured: 10 blocks 114.8 -> 90.7 ms, 4 blocks 8.7 -> 6.5 ms);
+            // parallel tempering is built with six only
+            const int producers = inst->split == 1 && d.pt == 0 ? 3 : 6;
             e = pc ? launch_sweep_quad_pc(d, inst->plan.nb, producers, s)
                    : launch_sweep_quad(d, inst->plan.nb, inst->wpb, s);
             break;

@@ -61,8 +61,12 @@ __device__ __forceinline__ void load_visit_ops(VisitOps &o, const BlockVisit &v,
     }
 }
 
-// Consumer visit of site s: the ring holds the threshold on the field itself.
-template <int s>
+// Consumer visit of site s: the ring holds the threshold on the field itself,
+// or, with parallel tempering (every lane at the temperature of its ladder
+// position, which the producers do not know), the draw's table position j*,
+// which the visit compares with the index of its own field: [idx >= j*] is
+// the update [u24 < Theta[idx]].  The replica's energy follows every flip.
+template <int s, bool PT = false>
 __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], const uint32_t (&x0)[8],
                                               const VisitOps &o)
 {
@@ -73,10 +77,15 @@ __device__ __forceinline__ void visit_site_pc(BlockVisit &v, uint32_t (&xc)[8], 
     for (int w = 0; w < (s + 3) / 4; ++w) f = __builtin_amdgcn_sdot4((int)o.w[w], (int)xc[w], f, false);
     // v.k2 holds -k2 here
     const int64_t Z = o.K + (int64_t)(f * 256) * v.sg2 + (int64_t)__mul24(o.meta, v.g) * v.k2;
-    const uint32_t xn = Z >= o.thr ? 1u : 0u;
+    uint32_t xn;
+    if constexpr (PT)  // (sites beyond N_ext hold INT64_MAX: never on)
+        xn = (int64_t)theta_index(Z, v.Bt, v.ish, v.irnd, v.hclo, v.hchi) >= o.thr ? 1u : 0u;
+    else
+        xn = Z >= o.thr ? 1u : 0u;
     const int32_t delta = (int32_t)xn - (int32_t)xo;
     xc[s >> 2] += (uint32_t)delta << (8 * (s & 3));
     v.g += __mul24(delta, o.meta);
+    if constexpr (PT) v.E = delta > 0 ? v.E - Z : (delta < 0 ? v.E + Z : v.E);
 }
 
 // Fields of the next block, accumulated on the matrix cores while the current
@@ -131,7 +140,7 @@ __device__ __forceinline__ void next_fields_step(NextFields<NB> &nf, const uint3
 #define PBIT_PC_PREFETCH 4
 #endif
 
-template <int LS, int NB, int... S>
+template <int LS, int NB, bool PT, int... S>
 __device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&x)[NB][8], NextFields<NB> &nf,
                                                const int64_t *ring, std::integer_sequence<int, S...>)
 {
@@ -141,7 +150,7 @@ __device__ __forceinline__ void visit_block_pc(BlockVisit &v, uint32_t (&x)[NB][
     // the operands of the first PF visits, then each visit reads those of the
     // visit PF places later into the slot it has just used
     ((S < PF ? load_visit_ops<S < PF ? S : 32, LS>(ops[S % PF], v, x0, ring) : void()), ...);
-    ((visit_site_pc<S>(v, x[0], x0, ops[S % PF]), load_visit_ops<S + PF, LS>(ops[S % PF], v, x0, ring),
+    ((visit_site_pc<S, PT>(v, x[0], x0, ops[S % PF]), load_visit_ops<S + PF, LS>(ops[S % PF], v, x0, ring),
       next_fields_step<S, NB>(nf, x), visit_fence<S, PBIT_PC_SCHED_WINDOW>()),
      ...);
 }
@@ -166,7 +175,7 @@ __device__ __forceinline__ int theta_floor_guess(uint32_t u)
 // a third entry those one position off, and an exact bisection over the whole
 // table the rest (flat tails, where many positions share a value: a few draws
 // in 10^6).  Sites at or beyond N_ext never flip.
-template <int NP, int KG>
+template <int NP, int KG, bool JSTAR>
 __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int t, int blk, int64_t *ring,
                                                const int32_t *th, uint32_t kround, uint64_t m2)
 {
@@ -240,8 +249,13 @@ __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int 
     // in 10^9) makes its wave redo that draw exactly.  The thresholds are
     // stored after all of them are known (stores between the computations
     // made the whole kernel a third slower, measured).
-    const ZtSweep zs = d.zsweep[t];
     int64_t h[E];
+    if constexpr (JSTAR) {
+        // parallel tempering: the table position itself
+#pragma unroll
+        for (int e = 0; e < E; ++e) h[e] = lo[e] + 1 - kThetaHalf;
+    } else {
+    const ZtSweep zs = d.zsweep[t];
     if (zs.fast) {
         bool near[E], any = false;
 #pragma unroll
@@ -258,6 +272,7 @@ __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int 
 #pragma unroll
         for (int e = 0; e < E; ++e) h[e] = field_threshold(2 * (lo[e] + 1 - kThetaHalf) - 1, zs);
     }
+    }
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
         if (p + NP * k < 8) {
@@ -273,15 +288,15 @@ __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int 
 // Producer p owns the Philox groups p, p + NP, p + 2 NP, ... below 8: the first
 // 8 - NP (KMAX - 1) producers take KMAX of them, the others one fewer (with
 // NP = 6, two per SIMD, the SIMDs then carry 3, 3 and 2 groups).
-template <int NP>
+template <int NP, bool JSTAR = false>
 __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, int t, int blk, int64_t *ring,
                                                    const int32_t *th, uint32_t kround, uint64_t m2)
 {
     constexpr int KMAX = (8 + NP - 1) / NP;
     if (p + NP * (KMAX - 1) < 8)
-        produce_groups<NP, KMAX>(d, p, t, blk, ring, th, kround, m2);
+        produce_groups<NP, KMAX, JSTAR>(d, p, t, blk, ring, th, kround, m2);
     else
-        produce_groups<NP, KMAX - 1>(d, p, t, blk, ring, th, kround, m2);
+        produce_groups<NP, KMAX - 1, JSTAR>(d, p, t, blk, ring, th, kround, m2);
 }
 
 // Producer p's share of the next J slab (quadratic kernel): loaded into
@@ -326,7 +341,7 @@ constexpr int quad_pc_waves()
 // One annealing run of replicas rbase + [0, 64) by a workgroup of
 // quad_pc_waves<PR>() waves, then the scoring of the final states.  smem must
 // hold quad_pc_lds_bytes<NB>() bytes.
-template <int NB, int PR>
+template <int NB, int PR, bool PT = false>
 __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, unsigned char *smem)
 {
     static_assert(PR == 3 || PR == 6, "3 or 6 producers");
@@ -361,7 +376,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
 
     const bool producer = wave > 0 && !(PR == 6 && wave == 4);
     const int pi = PR == 6 && wave > 4 ? wave - 2 : wave - 1;  // producer index 0 .. PR-1
-    if (producer) produce_thresholds<PR>(d, pi, 0, 0, ring, th, kround, m2);
+    if (producer) produce_thresholds<PR, PT>(d, pi, 0, 0, ring, th, kround, m2);
     __syncthreads();
 
     uint32_t x[NB][8];
@@ -386,6 +401,12 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     v.m2 = m2;
     v.wave = wave;
     v.nw = 1;
+    // parallel tempering: the replica's ladder position, the lane this lane
+    // keeps track of (the one at position lane mod L), the replica's energy
+    int32_t slot = 0, owner = lane;
+    v.E = 0;
+    v.Bt = 0;
+    if constexpr (PT) slot = lane & (d.pt - 1);
 
     if (wave == 0) block_fields<NB>(slabs, 0, x, v.F);  // fields of the first block
 
@@ -407,7 +428,8 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             nf.arow = slabs + b1 * SLAB + (lane & 31) * LS + (lane >> 5) * 16;
             nf.adiag = diag_arow<NB>(slabs + b1 * SLAB, lane);
             nf.load(blk);
-            visit_block_pc<LS, NB>(v, x, nf, ring + buf * 32 * 64, std::make_integer_sequence<int, 32>{});
+            if (PT && blk == 0) v.Bt = d.bladder[slot];  // this sweep's temperature
+            visit_block_pc<LS, NB, PT>(v, x, nf, ring + buf * 32 * 64, std::make_integer_sequence<int, 32>{});
 #pragma unroll
             for (int w = 0; w < 4; ++w) swap_halves(x[0][w], x[0][w + 4]);
             {
@@ -421,6 +443,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             }
             rotate_chunks<NB>(x);
             fields_from_acc(nf.acc0, nf.acc1, v.F);
+            if (PT && blk == NB - 1) pt_exchange(d, c / NB, kround, m2, v.E, owner, slot);  // after each sweep
         } else if (producer) {
             // the next block's thresholds, and the slab of the block after it
             // (at the end: slabs 0 and 1 for the scoring pass, no thresholds)
@@ -428,7 +451,8 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             const int blk2 = (c + 2) % NB;
             uint4 pf[slab_pieces_per_producer<NB, PR>()];
             load_slab<NB, PR>(pi, d.J + (size_t)blk2 * SLAB, pf);
-            if (c + 1 < total) produce_thresholds<PR>(d, pi, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
+            if (c + 1 < total)
+                produce_thresholds<PR, PT>(d, pi, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
             store_slab<NB, PR>(pi, slabs + b2 * SLAB, pf);
         }
         buf ^= 1;
@@ -479,6 +503,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
         d.rprofit[r] = pacc / 2;
         d.rfeas[r] = v.g <= sval ? 1 : 0;
         d.rg[r] = v.g;
+        if constexpr (PT) d.rslot[r] = slot;
     }
 }
 

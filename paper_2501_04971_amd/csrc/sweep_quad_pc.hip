@@ -5,25 +5,29 @@ namespace pbit {
 
 static_assert(quad_pc_lds_bytes<kMaxQuadBlocks>() <= 160 * 1024, "split layout exceeds the LDS of a CU");
 
-template <int NB, int PR>
+template <int NB, int PR, bool PT>
 __global__ __launch_bounds__(quad_pc_waves<PR>() * kWave) void sweep_quad_pc(const DevInstance d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    quad_run_pc<NB, PR>(d, blockIdx.x * kWave, smem);
+    quad_run_pc<NB, PR, PT>(d, blockIdx.x * kWave, smem);
 }
 
+// PT: parallel tempering (d.pt > 0), built with six producers only
 #define PBIT_QUAD_PC_CASE(nb)                                                               \
     case nb:                                                                                \
-        kern = producers == 6 ? reinterpret_cast<const void *>(&sweep_quad_pc<nb, 6>)      \
-                              : reinterpret_cast<const void *>(&sweep_quad_pc<nb, 3>);     \
+        kern = pt ? reinterpret_cast<const void *>(&sweep_quad_pc<nb, 6, true>)             \
+                  : (producers == 6 ? reinterpret_cast<const void *>(&sweep_quad_pc<nb, 6, false>) \
+                                    : reinterpret_cast<const void *>(&sweep_quad_pc<nb, 3, false>)); \
         lds = quad_pc_lds_bytes<nb>();                                                      \
         break;
 
 // One workgroup per 64 replicas, with 3 producer waves (4 waves in all) or 6
-// (8 waves).
+// (8 waves); parallel tempering takes 6.
 hipError_t launch_sweep_quad_pc(const DevInstance &d, int nb, int producers, hipStream_t stream)
 {
+    const bool pt = d.pt > 0;
     if (producers != 3 && producers != 6) return hipErrorInvalidValue;
+    if (pt && producers != 6) return hipErrorInvalidValue;
     const void *kern = nullptr;
     size_t lds = 0;
     switch (nb) {

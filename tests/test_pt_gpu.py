@@ -1,7 +1,9 @@
 """Parallel tempering as the machine inside Algorithm 1 on the GPU, against the
 oracle bit for bit: every replica's final state and residual, its ladder
 position, the chains' samples' residual sums, the multipliers each round and
-the best record."""
+the best record, in the split layout (the default: producers hand over each
+draw's table position, the visiting wave compares it with its own field's
+index at its lane's temperature) and in the plain one."""
 import sys
 from fractions import Fraction
 
@@ -20,17 +22,19 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("n,L,R,wpb", [(40, 4, 64, 0), (70, 16, 128, 1), (100, 64, 128, 0), (33, 2, 96, 0)])
-def test_parallel_tempering_matches_oracle(need_gpu, n, L, R, wpb):
+@pytest.mark.parametrize("n,L,R,wpb,split", [(40, 4, 64, 0, -1), (70, 16, 128, 1, -1), (100, 64, 128, 0, -1),
+                                             (33, 2, 96, 0, -1), (300, 32, 128, 0, -1), (40, 4, 64, 1, 0),
+                                             (100, 64, 128, 4, 0)])
+def test_parallel_tempering_matches_oracle(need_gpu, n, L, R, wpb, split):
     prob = G.qkp(n, Fraction(1, 2), G.rng_for(994, n))
     par = G.Params(replicas=R, sweeps=40, beta=Fraction(10), eta=Fraction(20), pt_slots=L)
     rounds = 3
-    say(f"[pt] n={n} L={L} R={R} wpb={wpb}")
+    say(f"[pt] n={n} L={L} R={R} wpb={wpb} split={split}")
     ref = O.saim(prob, par, rounds, nthreads=8)
     prog = ref["program"]
     inst = B.Instance(prob, par)
-    if wpb:
-        inst.set_tiling(wpb)
+    if wpb or split != -1:
+        inst.set_tiling(wpb, -1, split)
     for k in range(rounds):
         assert [int(v) for v in inst.get_lambda()] == ref["rounds"][k]["lq"], f"round {k}: multipliers"
         inst.sample_round()
