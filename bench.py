@@ -138,8 +138,8 @@ def host_cpu():
     return os.cpu_count() or 1, usable, model
 
 
-# A one-GPU machine grants its process a share of 16 host CPUs whatever the machine
-# has; the CPU leg uses every CPU it may run on, up to that share.
+# The CPU leg uses every host CPU this process may run on, up to 16 (the share
+# a one-GPU host grants a process, whatever the machine has).
 HOST_CPU_SHARE = 16
 
 
