@@ -1,7 +1,7 @@
 // Producer/consumer form of the quadratic annealing run, for launches that
 // leave SIMDs idle (one wave of 64 replicas per CU): a workgroup is one
-// consumer wave that walks the sites of its 64 replicas, plus three (or six,
-// two per SIMD) producer waves on the CU's other SIMDs that do the part of
+// consumer wave that walks the sites of its 64 replicas, plus six (two per
+// SIMD, the default) or three producer waves on the CU's other SIMDs that do the part of
 // every visit that does not depend on the state, one block of 32 sites ahead:
 //
 //  * the Philox4x32-10 draw u24 of the visit (same counters as everywhere);
