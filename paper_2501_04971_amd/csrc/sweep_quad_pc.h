@@ -27,10 +27,15 @@
 
 namespace pbit {
 
+// The threshold table of the split quadratic kernel is stored as pairs:
+// 8-byte entry k holds Theta[k] and Theta[k + 1], so that a producer's probe
+// of two adjacent entries is one aligned 64-bit read.
+constexpr int kThetaPairBytes = kThetaLen * 8 + 8;  // rounded up to 16 bytes
+
 template <int NB>
 constexpr size_t quad_pc_lds_bytes()
 {
-    return (size_t)kThetaBytes + (size_t)NB * 32 * 32 + 3 * (size_t)1024 * (NB + 1) + kRingBytes;
+    return (size_t)kThetaPairBytes + (size_t)NB * 32 * 32 + 3 * (size_t)1024 * (NB + 1) + kRingBytes;
 }
 
 // Operands of one consumer visit, read from LDS a few visits ahead so that
@@ -175,10 +180,12 @@ __device__ __forceinline__ int theta_floor_guess(uint32_t u)
 // a third entry those one position off, and an exact bisection over the whole
 // table the rest (flat tails, where many positions share a value: a few draws
 // in 10^6).  Sites at or beyond N_ext never flip.
-template <int NP, int KG, bool JSTAR>
+// PAIR: th is the pair table (entry k at th[2k], th[2k + 1] = Theta[k + 1]).
+template <int NP, int KG, bool JSTAR, bool PAIR>
 __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int t, int blk, int64_t *ring,
                                                const int32_t *th, uint32_t kround, uint64_t m2)
 {
+    auto entry = [th](int k) { return (uint32_t)th[PAIR ? 2 * k : k]; };
     constexpr int E = 4 * KG;
     const int lane = threadIdx.x & 63;
     const uint32_t cbase = (uint32_t)t * (uint32_t)d.nq;
@@ -203,7 +210,15 @@ __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int 
         // draw when th[g] <= u < th[g + 1] (position g); otherwise dir says on
         // which side the position lies (th is non-decreasing)
         const int g = gs[e];
-        const uint32_t t1 = (uint32_t)th[g], t2 = (uint32_t)th[g + 1];
+        uint32_t t1, t2;
+        if constexpr (PAIR) {
+            const uint2 pr = *reinterpret_cast<const uint2 *>(th + 2 * g);
+            t1 = pr.x;
+            t2 = pr.y;
+        } else {
+            t1 = (uint32_t)th[g];
+            t2 = (uint32_t)th[g + 1];
+        }
         const bool skip = p + NP * (e >> 2) >= 8;  // a discarded group needs no search
         dir[e] = skip ? 0 : (t1 > u[e] ? -1 : (t2 <= u[e] ? 1 : 0));
         lo[e] = g;
@@ -219,7 +234,7 @@ __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int 
         for (int e = 0; e < E; ++e) {
             if (dir[e] != 0) {
                 const int g = gs[e];
-                const uint32_t t3 = (uint32_t)th[dir[e] < 0 ? g - 1 : g + 2];
+                const uint32_t t3 = entry(dir[e] < 0 ? g - 1 : g + 2);
                 const bool ok = dir[e] < 0 ? t3 <= u[e] : u[e] < t3;
                 lo[e] = ok ? g + dir[e] : 0;
                 hi[e] = ok ? g + dir[e] : kThetaLen - 1;
@@ -237,7 +252,7 @@ __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int 
         for (int e = 0; e < E; ++e) {
             if (lo[e] < hi[e]) {
                 const int mid = (lo[e] + hi[e] + 1) >> 1;
-                const bool le = (uint32_t)th[mid] <= u[e];
+                const bool le = entry(mid) <= u[e];
                 lo[e] = le ? mid : lo[e];
                 hi[e] = le ? hi[e] : mid - 1;
             }
@@ -288,15 +303,15 @@ __device__ __forceinline__ void produce_groups(const DevInstance &d, int p, int 
 // Producer p owns the Philox groups p, p + NP, p + 2 NP, ... below 8: the first
 // 8 - NP (KMAX - 1) producers take KMAX of them, the others one fewer (with
 // NP = 6, two per SIMD, the SIMDs then carry 3, 3 and 2 groups).
-template <int NP, bool JSTAR = false>
+template <int NP, bool JSTAR = false, bool PAIR = false>
 __device__ __forceinline__ void produce_thresholds(const DevInstance &d, int p, int t, int blk, int64_t *ring,
                                                    const int32_t *th, uint32_t kround, uint64_t m2)
 {
     constexpr int KMAX = (8 + NP - 1) / NP;
     if (p + NP * (KMAX - 1) < 8)
-        produce_groups<NP, KMAX, JSTAR>(d, p, t, blk, ring, th, kround, m2);
+        produce_groups<NP, KMAX, JSTAR, PAIR>(d, p, t, blk, ring, th, kround, m2);
     else
-        produce_groups<NP, KMAX - 1, JSTAR>(d, p, t, blk, ring, th, kround, m2);
+        produce_groups<NP, KMAX - 1, JSTAR, PAIR>(d, p, t, blk, ring, th, kround, m2);
 }
 
 // Producer p's share of the next J slab (quadratic kernel): loaded into
@@ -348,16 +363,19 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
     constexpr int NP = NB * 32;
     constexpr int LS = NP + 16;
     constexpr int SLAB = 1024 * (NB + 1);
-    int32_t *th = reinterpret_cast<int32_t *>(smem);
-    int64_t *site = reinterpret_cast<int64_t *>(smem + kThetaBytes);
-    int8_t *slabs = reinterpret_cast<int8_t *>(smem + kThetaBytes + NP * 32);  // three buffers
-    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaBytes + NP * 32 + 3 * SLAB);
+    int32_t *th = reinterpret_cast<int32_t *>(smem);  // pair table
+    int64_t *site = reinterpret_cast<int64_t *>(smem + kThetaPairBytes);
+    int8_t *slabs = reinterpret_cast<int8_t *>(smem + kThetaPairBytes + NP * 32);  // three buffers
+    int64_t *ring = reinterpret_cast<int64_t *>(smem + kThetaPairBytes + NP * 32 + 3 * SLAB);
 
     // the slab of block step c (block c % NB) sits in buffer c % 3 during steps
     // c - 1 (the next block's fields) and c (its in-block couplings)
     copy_slab<NB>(d.J, 0, slabs);
     copy_slab<NB>(d.J, 1 % NB, slabs + SLAB);
-    for (int e = threadIdx.x; e < kThetaLen; e += blockDim.x) th[e] = d.theta[e];
+    for (int e = threadIdx.x; e < kThetaLen; e += blockDim.x) {
+        th[2 * e] = d.theta[e];
+        th[2 * e + 1] = d.theta[e + 1 < kThetaLen ? e + 1 : e];
+    }
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(d.site);
         uint4 *dst = reinterpret_cast<uint4 *>(site);
@@ -376,7 +394,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
 
     const bool producer = wave > 0 && !(PR == 6 && wave == 4);
     const int pi = PR == 6 && wave > 4 ? wave - 2 : wave - 1;  // producer index 0 .. PR-1
-    if (producer) produce_thresholds<PR, PT>(d, pi, 0, 0, ring, th, kround, m2);
+    if (producer) produce_thresholds<PR, PT, true>(d, pi, 0, 0, ring, th, kround, m2);
     __syncthreads();
 
     uint32_t x[NB][8];
@@ -452,7 +470,7 @@ __device__ __forceinline__ void quad_run_pc(const DevInstance &d, int rbase, uns
             uint4 pf[slab_pieces_per_producer<NB, PR>()];
             load_slab<NB, PR>(pi, d.J + (size_t)blk2 * SLAB, pf);
             if (c + 1 < total)
-                produce_thresholds<PR, PT>(d, pi, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
+                produce_thresholds<PR, PT, true>(d, pi, t1, blk1, ring + (buf ^ 1) * 32 * 64, th, kround, m2);
             store_slab<NB, PR>(pi, slabs + b2 * SLAB, pf);
         }
         buf ^= 1;
