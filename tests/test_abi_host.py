@@ -183,3 +183,7 @@ def test_parallel_tempering_settings_and_plan(lib):
         prog = O.build_program(prob, par)
         assert info.lq_max == prog.lq_max and info.shift == prog.S
         assert info.out_slot < info.out_bytes
+    # batches run annealing members only
+    par = G.Params(replicas=64, sweeps=10, beta=Fraction(7), pt_slots=4)
+    assert B.pbit_batch_workspace_bytes([prob, prob], [G.Params(replicas=64, sweeps=10), par]) == 0
+    assert "single instances" in lib.pbit_last_error().decode()
