@@ -1,0 +1,72 @@
+"""GPU parity on seeded random shapes: sizes, densities, constraint counts,
+replica and sweep counts, temperatures, steps and launch layouts drawn at
+random (one generator per case), each run for two rounds against the oracle
+bit for bit.  Shapes the library refuses are drawn again."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2501_04971_amd import binding as B
+from paper_2501_04971_amd import generators as G
+from test_parity_gpu import assert_round_equal, say
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+BETAS = [Fraction(0), Fraction(1, 2), Fraction(5), Fraction(10), Fraction(50)]
+ETAS = [Fraction(0), Fraction(1, 20), Fraction(1, 2), Fraction(20)]
+DENS = [Fraction(1, 8), Fraction(1, 4), Fraction(1, 2), Fraction(3, 4), Fraction(1)]
+
+
+def draw(case: int):
+    rng = np.random.default_rng([97, case])
+    while True:
+        if case % 2 == 0:
+            n = int(rng.integers(1, 321))
+            prob = G.qkp(n, DENS[int(rng.integers(len(DENS)))], G.rng_for(970, case))
+            alpha = Fraction(2)
+        else:
+            n, m = int(rng.integers(1, 201)), int(rng.integers(1, 33))
+            prob = G.mkp(n, m, G.rng_for(971, case))
+            alpha = Fraction(5)
+        par = G.Params(replicas=int(rng.integers(1, 200)), sweeps=int(rng.integers(1, 26)),
+                       beta=BETAS[int(rng.integers(len(BETAS)))], eta=ETAS[int(rng.integers(len(ETAS)))],
+                       alpha=alpha, seed=int(rng.integers(1 << 31)), instance_id=case)
+        layout = int(rng.integers(2))  # 0: the library's choice, 1: the plain layout
+        try:
+            B.pbit_plan(prob, par)
+        except B.PbitError:
+            continue
+        return prob, par, layout
+
+
+@pytest.mark.parametrize("case", range(48))
+def test_random_shape(need_gpu, case):
+    prob, par, layout = draw(case)
+    say(f"[random] case {case}: kind {prob.kind} n={prob.n} m={prob.m} R={par.replicas} T={par.sweeps} "
+        f"beta={par.beta} eta={par.eta} layout={'plain' if layout else 'default'}")
+    rounds = 2
+    ref = O.saim(prob, par, rounds, nthreads=8)
+    inst = B.Instance(prob, par)
+    try:
+        if layout:
+            inst.set_tiling(0, -1, 0)
+        for k in range(rounds):
+            lam = inst.get_lambda()
+            inst.sample_round()
+            out = inst.round_outputs()
+            inst.update_lambda()
+            out["lq"] = lam
+            assert_round_equal(ref["program"], ref["rounds"][k], out, k)
+        assert [int(v) for v in inst.get_lambda()] == ref["lq"]
+        best = inst.best_feasible()
+        if ref["best"] is None:
+            assert best is None
+        else:
+            assert best is not None and best[0] == ref["best"][0]
+            assert best[2] == ref["best"][1] and best[3] == ref["best"][2]
+            assert (best[1] == ref["best"][3]).all()
+    finally:
+        inst.close()
