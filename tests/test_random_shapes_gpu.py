@@ -70,3 +70,23 @@ def test_random_shape(need_gpu, case):
             assert (best[1] == ref["best"][3]).all()
     finally:
         inst.close()
+
+
+def test_random_batch(need_gpu):
+    """Twenty-four random members (the shapes above, other seeds) with round
+    budgets of one to three, one persistent batch replayed as a graph: every
+    member ends where the oracle's loop for it alone ends."""
+    from test_batch_gpu import verify_final
+    members = []
+    for case in range(100, 124):
+        prob, par, _ = draw(case)
+        members.append((prob, par, 1 + case % 3))
+    say(f"[random] batch of {len(members)} members")
+    refs = [O.saim(p, q, K, nthreads=8) for p, q, K in members]
+    batch = B.Batch([p for p, _, _ in members], [q for _, q, _ in members], rounds=[K for _, _, K in members])
+    try:
+        batch.run(4, use_graph=True)
+        assert (batch.rounds_left() == 0).all()
+        verify_final(batch, members, refs)
+    finally:
+        batch.close()
