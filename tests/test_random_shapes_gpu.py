@@ -90,3 +90,47 @@ def test_random_batch(need_gpu):
         verify_final(batch, members, refs)
     finally:
         batch.close()
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_random_tempering(need_gpu, case):
+    """Parallel tempering on random quadratic shapes: chain length L of 2..64,
+    R a multiple of L, random sweeps, temperatures, steps and layout."""
+    rng = np.random.default_rng([98, case])
+    n = int(rng.integers(1, 321))
+    prob = G.qkp(n, DENS[int(rng.integers(len(DENS)))], G.rng_for(972, case))
+    L = int(2 ** rng.integers(1, 7))
+    par = G.Params(replicas=L * int(rng.integers(1, max(2, 200 // L + 1))), sweeps=int(rng.integers(1, 26)),
+                   beta=BETAS[1 + int(rng.integers(len(BETAS) - 1))], eta=ETAS[int(rng.integers(len(ETAS)))],
+                   seed=int(rng.integers(1 << 31)), instance_id=case, pt_slots=L)
+    layout = int(rng.integers(2))
+    say(f"[random] tempering case {case}: n={n} L={L} R={par.replicas} T={par.sweeps} beta={par.beta} "
+        f"eta={par.eta} layout={'plain' if layout else 'default'}")
+    rounds = 2
+    ref = O.saim(prob, par, rounds, nthreads=8)
+    inst = B.Instance(prob, par)
+    try:
+        if layout:
+            inst.set_tiling(0, -1, 0)
+        for k in range(rounds):
+            assert [int(v) for v in inst.get_lambda()] == ref["rounds"][k]["lq"], f"round {k}: multipliers"
+            inst.sample_round()
+            out = inst.round_outputs()
+            inst.update_lambda()
+            e = ref["rounds"][k]
+            x = B.unpack_bits(out["x_bits"], ref["program"].n_ext)
+            bad = np.nonzero((x != e["x"]).any(axis=1))[0]
+            assert bad.size == 0, f"round {k}: {bad.size} replicas differ, first {bad[:4]}"
+            assert (out["g"] == e["g"]).all(), f"round {k}: residuals"
+            assert (out["slot"] == e["slot"]).all(), f"round {k}: ladder positions"
+            assert (out["profit"] == e["profit"]).all()
+            assert (out["feasible"].astype(bool) == e["feasible_mask"]).all()
+            assert [int(v) for v in out["G"]] == e["G"], f"round {k}: residual sums of the samples"
+        assert [int(v) for v in inst.get_lambda()] == ref["lq"]
+        best = inst.best_feasible()
+        if ref["best"] is None:
+            assert best is None
+        else:
+            assert best is not None and best[0] == ref["best"][0] and best[2:] == (ref["best"][1], ref["best"][2])
+    finally:
+        inst.close()
